@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""Throughput of the batched S-MNN least-squares solve (forward + backward) on one MI355X.
+
+One step = smnn_forward + smnn_backward over the whole synthetic batch, with
+every input already resident in HBM (dl/dy = 2 y^(0), the gradient of
+sum_t (y_t^(0))^2, is formed once from the first solution and is an input of
+the backward like any other).  The default workload is the headline
+configuration: 512 x 3 = 1536 instances, T = 10,000 steps, R = 2.
+
+Prints ONE JSON line (rank 0).  Besides the contract fields it carries
+  roofline      the dominant kernel's algorithmic bytes per launch divided by
+                its mean launch time (hipEvent pairs recorded by the library
+                around every launch during a second, traced copy of the timed
+                steps), against the 8 TB/s HBM peak;
+  cpu_baseline  the oracle (oracle/banded.c, OpenMP) timed on a bounded
+                sample of the same workload on the host's cores;
+  modes         steps/s, ms/step and sampled error against the FP64 oracle
+                for every solver mode measured (the headline mode included).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solved ODE steps/sec fwd+bwd (T=10k, R=2); % HBM roofline; err vs FP64"
+HBM_PEAK_GBS = 8000.0
+RHS_BETA, RHS_RESID, RHS_G, RHS_GRESID = 0, 1, 2, 3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------ byte model
+def kernel_bytes(rec, plan, io):
+    """Algorithmic HBM bytes of one traced launch: every array the launch must
+    read once plus every array it must write once (metadata excluded)."""
+    kind, level, rhs, out = rec[0], rec[1], rec[2], rec[3]
+    K = plan.k
+    Q = K * (K + 1) // 2
+    REC = Q + K * K
+    lv = plan.levels                       # [(nodes, chunks)] per level
+    S, G0 = lv[0]
+    N = plan.n_inst
+    n = lambda l: lv[l][0] if l < len(lv) else 0
+    per_inst = N * (plan.n_init + 3) * io
+    if kind == "reduce0":
+        el = K + 1 + (1 if rhs in (RHS_BETA, RHS_RESID) else 0) + (K if rhs in (RHS_G, RHS_GRESID) else 0) \
+            + (K if rhs in (RHS_RESID, RHS_GRESID) else 0)
+        w = n(1) * K * 8 + (n(1) * REC * 8 if rhs == RHS_BETA else 0)
+        return S * el * io + per_inst + w
+    if kind == "reduceN":
+        w = n(level + 1) * K * 8 + (n(level + 1) * REC * 8 if rhs == RHS_BETA else 0)
+        return n(level) * (REC + K) * 8 + w
+    if kind == "backsubN":
+        return n(level) * (REC + K) * 8 + n(level + 1) * K * 8 + n(level) * K * 8
+    if kind == "backsub0":
+        grad = out == 1
+        el = K + 1 + (1 if (rhs in (RHS_BETA, RHS_RESID) or grad) else 0) + (K if rhs in (RHS_G, RHS_GRESID) else 0) \
+            + (K if rhs in (RHS_RESID, RHS_GRESID) else 0) + (K if grad else 0)
+        wr = (K + 2) * S * io + G0 * 3 * 8 + N * plan.n_init * io if grad else K * S * io
+        return S * el * io + per_inst + n(1) * K * 8 + wr
+    if kind == "dw_reduce":
+        return G0 * 3 * 8 + N * 3 * io
+    return 0
+
+
+# ------------------------------------------------------------- workload
+def make_workload(name, n_inst=None, T=None):
+    from workloads import config
+    return config(name, n_inst=n_inst, T=T)
+
+
+def describe(name, bt, mode):
+    sizes = {"h": "512x3", "c1": "512x3", "c2": "256x128", "c3": "2048", "c4": "4x8", "c0": "1"}
+    T = int(bt.T[0]) if (bt.T == bt.T[0]).all() else "ragged %d..%d" % (bt.T.min(), bt.T.max())
+    return {"workload": "%s: %s = %d instances, T=%s, R=%d, forward+adjoint, mode %s"
+                        % (name, sizes.get(name, "?"), bt.n_inst, T, bt.R, mode),
+            "instances": int(bt.n_inst), "steps_per_instance": T, "order_R": int(bt.R),
+            "total_steps": int(bt.total_steps), "mode": mode,
+            "inputs": "seeded synthetic (workloads.config('%s'))" % name}
+
+
+# --------------------------------------------------------------- GPU run
+def run_mode(bt, mode, steps, warmup, sample_idx):
+    import numpy as np
+    import torch
+    from paper_2410_06074_amd import Plan
+    from oracle import banded
+    from tests import metrics
+
+    dev = torch.device("cuda:0")
+    dt = torch.float32 if mode == "fp32r" else torch.float64
+    io = 4 if mode == "fp32r" else 8
+    steps_arg = int(bt.T[0]) if (bt.T == bt.T[0]).all() else bt.T
+    plan = Plan(bt.R, bt.n_init, bt.n_inst, steps_arg, mode=mode)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt)
+    c, b, h, u0, w = t(bt.c), t(bt.b), t(bt.h), t(bt.u0), t(bt.w)
+    S, K = plan.total_steps, plan.k
+    y = torch.empty((S, K), dtype=dt, device=dev)
+    fac, ws = plan.new_factor(dev), plan.new_workspace(dev)
+    dc, db, dh = torch.empty_like(c), torch.empty_like(b), torch.empty_like(h)
+    du0, dw = torch.empty_like(u0), torch.empty_like(w)
+    plan.forward(c, b, h, u0, w, y, fac, ws)
+    gy = torch.zeros_like(y)
+    gy[:, 0] = 2.0 * y[:, 0]
+    torch.cuda.synchronize()
+
+    def step():
+        plan.forward(c, b, h, u0, w, y, fac, ws)
+        plan.backward(c, b, h, u0, w, y, fac, gy, dc, db, dh, du0, dw, ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+
+    # traced copy of the timed steps: one event pair around every launch
+    launches_per_step = 64 * max(1, len(plan.levels))
+    plan.trace(launches_per_step * steps)
+    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e2.record()
+    for _ in range(steps):
+        step()
+    e3.record()
+    torch.cuda.synchronize()
+    ms_traced = e2.elapsed_time(e3) / steps
+    trace = plan.trace_read(launches_per_step * steps + 16)
+    plan.trace(0)
+    per_kind = {}
+    for r in trace:
+        key = "%s/l%d/rhs%d/out%d" % r[:4]
+        d = per_kind.setdefault(key, {"ms": 0.0, "n": 0, "bytes": kernel_bytes(r, plan, io)})
+        d["ms"] += r[4]
+        d["n"] += 1
+    step_bytes = sum(v["bytes"] * v["n"] for v in per_kind.values()) / steps
+
+    # error against the FP64 oracle on sampled instances (the oracle runs on the
+    # same, possibly float32-rounded, inputs)
+    yn = y.double().cpu().numpy()
+    sub = bt.subset(sample_idx)
+    if mode == "fp32r":
+        sub = sub.astype(np.float32).astype(np.float64)
+    ref = banded.solve(sub)
+    o, so = bt.offsets, sub.offsets
+    err = 0.0
+    for j, i in enumerate(sample_idx):
+        err = max(err, max(metrics.rel_by_order(yn[o[i]:o[i + 1]], ref[so[j]:so[j + 1]], K)))
+    return {"plan": plan, "ms": ms, "ms_traced": ms_traced, "per_kind": per_kind, "step_bytes": step_bytes,
+            "err": err, "levels": plan.levels, "chunk": plan.chunk, "refine": plan.refine_steps}
+
+
+def roofline(res):
+    dom_key, dom = max(res["per_kind"].items(), key=lambda kv: kv[1]["ms"])
+    avg_ms = dom["ms"] / dom["n"]
+    achieved = dom["bytes"] / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": dom_key, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": int(dom["bytes"]), "avg_launch_ms": round(avg_ms, 5),
+            "share_of_step": round(dom["ms"] / max(1e-9, sum(v["ms"] for v in res["per_kind"].values())), 3)}
+
+
+# ------------------------------------------------------------ CPU baseline
+def cpu_baseline(bt, target_s=15.0):
+    import numpy as np
+    from oracle import banded
+    probe = bt.subset(list(range(min(8, bt.n_inst))))
+    g = np.zeros_like(probe.c)
+    t0 = time.perf_counter()
+    banded.grad(probe, g)
+    dt = max(time.perf_counter() - t0, 1e-6)
+    per_inst = dt / probe.n_inst
+    n = int(min(bt.n_inst, max(probe.n_inst, target_s / per_inst)))
+    idx = list(range(n))
+    sub = bt.subset(idx)
+    gy = np.zeros_like(sub.c)
+    t0 = time.perf_counter()
+    out = banded.grad(sub, gy)             # forward solve + adjoint + gradients
+    dt = time.perf_counter() - t0
+    return {"value": round(sub.total_steps / dt, 1), "unit": "steps/s", "cores": banded.threads(),
+            "kind": "oracle",
+            "sample": "%d of %d instances (T=%d each), banded-QR oracle forward+adjoint+gradients, %.1f s"
+                      % (n, bt.n_inst, int(bt.T[0]), dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="h", choices=["h", "c1", "c2", "c3", "c4"])
+    ap.add_argument("--mode", default="fp64r", choices=["fp64", "fp64r", "fp32r"])
+    ap.add_argument("--side-modes", default="fp64,fp32r", help="extra modes measured (comma list, '' for none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the solve is per-instance independent and this build has no "
+              "multi-GPU path (see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        return 2
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    import paper_2410_06074_amd
+    paper_2410_06074_amd.lib()
+
+    log("generating workload", args.config)
+    bt = make_workload(args.config)
+    sample = sorted({0, bt.n_inst // 2, bt.n_inst - 1})
+    modes = [args.mode] + [m for m in args.side_modes.split(",") if m and m != args.mode]
+    results = {}
+    for m in modes:
+        log("mode", m)
+        results[m] = run_mode(bt, m, args.steps, args.warmup, sample)
+        r = results[m]
+        log("  %.3f ms/step (traced %.3f), %.3e steps/s, err %.2e, levels %s"
+            % (r["ms"], r["ms_traced"], bt.total_steps / (r["ms"] * 1e-3), r["err"], r["levels"]))
+    head = results[args.mode]
+    value = bt.total_steps / (head["ms"] * 1e-3)
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.mode == "fp32r" else "f64",
+        "data": "synthetic",
+        "config": describe(args.config, bt, args.mode),
+        "err_vs_fp64_oracle": head["err"],
+        "roofline": roofline(head),
+        "step_hbm_bytes_algorithmic": int(head["step_bytes"]),
+        "step_bandwidth_frac": round(head["step_bytes"] / (head["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "modes": {m: {"steps_per_s": round(bt.total_steps / (r["ms"] * 1e-3), 1), "ms_per_step": round(r["ms"], 5),
+                      "err_vs_fp64_oracle": r["err"], "refine_steps": r["refine"], "chunk": r["chunk"],
+                      "roofline_frac": roofline(r)["frac"],
+                      "step_bandwidth_frac": round(r["step_bytes"] / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                      "traced_ms_per_step": round(r["ms_traced"], 5)}
+                  for m, r in results.items()},
+        "kernels": {k: {"avg_ms": round(v["ms"] / v["n"], 5), "launches": v["n"],
+                        "gbs": round(v["bytes"] / (v["ms"] / v["n"] * 1e-3) / 1e9, 1)}
+                    for k, v in sorted(head["per_kind"].items(), key=lambda kv: -kv[1]["ms"])},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        line["cpu_baseline"] = cpu_baseline(bt, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

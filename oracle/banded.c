@@ -16,6 +16,9 @@
  *  oracle_grad    -- y, the adjoint lam = M^{-1} g of Eq. 14 with M = R^T R,
  *                    and the closed-form per-row gradients (same formulas as
  *                    oracle/dense.py grad_rows).
+ *  oracle_cond    -- an estimate of the 2-norm condition number of the normal
+ *                    matrix M = A^T W A = R^T R: power iteration on M and on
+ *                    M^{-1} (both applied through the triangular factor).
  *
  * Pinned in tests/test_oracle_banded.py against the dense oracle (small T),
  * exact polynomial recovery (any T) and Table 5.
@@ -240,6 +243,84 @@ int oracle_grad(int R, int n_init, int64_t N, const int64_t* off, const double* 
     const int64_t o = off[i], T = off[i + 1] - off[i];
     fails += solve_one(R, n_init, T, c + o * k, d + o, s + o, u0 + i * n_init, w + 3 * i, y + o * k,
                        lam + o * k, g + o * k, dc + o * k, dd + o, ds + o, du0 + i * n_init, dw + 3 * i);
+  }
+  return fails;
+}
+
+
+static void apply_M(int k, int64_t T, const double* Rd, const double* Ro, const double* v, double* tmp, double* out) {
+  /* out = R^T (R v) */
+  for (int64_t t = 0; t < T; ++t)
+    for (int i = 0; i < k; ++i) {
+      double acc = 0.0;
+      for (int j = i; j < k; ++j) acc += Rd[(t * k + i) * k + j] * v[t * k + j];
+      if (t + 1 < T)
+        for (int j = 0; j < k; ++j) acc += Ro[(t * k + i) * k + j] * v[(t + 1) * k + j];
+      tmp[t * k + i] = acc;
+    }
+  for (int64_t t = 0; t < T; ++t)
+    for (int j = 0; j < k; ++j) {
+      double acc = 0.0;
+      for (int i = 0; i <= j; ++i) acc += Rd[(t * k + i) * k + j] * tmp[t * k + i];
+      if (t > 0)
+        for (int i = 0; i < k; ++i) acc += Ro[((t - 1) * k + i) * k + j] * tmp[(t - 1) * k + i];
+      out[t * k + j] = acc;
+    }
+}
+
+static double normalize(int64_t n, double* v) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += v[i] * v[i];
+  s = sqrt(s);
+  if (s > 0)
+    for (int64_t i = 0; i < n; ++i) v[i] /= s;
+  return s;
+}
+
+static double cond_one(int R, int n_init, int64_t T, const double* c, const double* d, const double* s,
+                       const double* u0, const double* w, int iters) {
+  const int k = R + 1;
+  const int64_t n = T * k;
+  double* Rd = (double*)malloc(sizeof(double) * n * k);
+  double* Ro = (double*)malloc(sizeof(double) * n * k);
+  double* z = (double*)malloc(sizeof(double) * n);
+  double* v = (double*)malloc(sizeof(double) * n);
+  double* t1 = (double*)malloc(sizeof(double) * n);
+  double* t2 = (double*)malloc(sizeof(double) * n);
+  double kappa = -1.0;
+  if (Rd && Ro && z && v && t1 && t2) {
+    factor(R, n_init, T, c, d, s, u0, w, Rd, Ro, z);
+    double lmax = 0.0, lmin_inv = 0.0;
+    for (int64_t i = 0; i < n; ++i) v[i] = 1.0 + 0.5 * sin(0.7 * (double)i);
+    normalize(n, v);
+    for (int it = 0; it < iters; ++it) {  /* largest eigenvalue of M */
+      apply_M(k, T, Rd, Ro, v, t1, t2);
+      lmax = normalize(n, t2);
+      memcpy(v, t2, sizeof(double) * n);
+    }
+    for (int64_t i = 0; i < n; ++i) v[i] = 1.0 + 0.5 * cos(1.3 * (double)i);
+    normalize(n, v);
+    for (int it = 0; it < iters; ++it) {  /* largest eigenvalue of M^{-1} */
+      fwd_solve_T(k, T, Rd, Ro, v, t1);
+      back_solve(k, T, Rd, Ro, t1, t2);
+      lmin_inv = normalize(n, t2);
+      memcpy(v, t2, sizeof(double) * n);
+    }
+    kappa = lmax * lmin_inv;
+  }
+  free(Rd); free(Ro); free(z); free(v); free(t1); free(t2);
+  return kappa;
+}
+
+int oracle_cond(int R, int n_init, int64_t N, const int64_t* off, const double* c, const double* d,
+                const double* s, const double* u0, const double* w, int iters, double* kappa) {
+  const int k = R + 1;
+  int fails = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : fails)
+  for (int64_t i = 0; i < N; ++i) {
+    const int64_t o = off[i], T = off[i + 1] - off[i];
+    kappa[i] = cond_one(R, n_init, T, c + o * k, d + o, s + o, u0 + i * n_init, w + 3 * i, iters);
+    fails += kappa[i] < 0;
   }
   return fails;
 }

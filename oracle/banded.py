@@ -39,6 +39,8 @@ def lib():
         L.oracle_grad.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ip] + [dp] * 13
         L.oracle_grad.restype = ctypes.c_int
         L.oracle_max_threads.restype = ctypes.c_int
+        L.oracle_cond.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ip] + [dp] * 5 + [ctypes.c_int, dp]
+        L.oracle_cond.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -82,6 +84,18 @@ def grad(batch, gy) -> dict:
     if rc:
         raise MemoryError("banded oracle: allocation failed")
     return out
+
+
+def cond(batch, iters: int = 60) -> np.ndarray:
+    """Estimated 2-norm condition number of each instance's normal matrix."""
+    c, b, h, u0, w, off = _arrays(batch)
+    kappa = np.zeros(batch.n_inst)
+    rc = lib().oracle_cond(batch.R, batch.n_init, batch.n_inst,
+                           off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                           _p(c), _p(b), _p(h), _p(u0), _p(w), int(iters), _p(kappa))
+    if rc:
+        raise MemoryError("banded oracle: allocation failed")
+    return kappa
 
 
 def threads() -> int:

@@ -1,0 +1,377 @@
+// C-ABI of libsmnn (include/smnn.h): plan creation, buffer layout and the
+// launch sequence of the forward and backward passes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/smnn.h"
+#include "smnn_core.h"
+#include "smnn_internal.h"
+#include "smnn_levels.h"
+
+using namespace smnn;
+
+struct smnn_plan {
+  int R = 0, K = 0, n_init = 0, mode = 0, refine = 0, L = 8;
+  int64_t N = 0, S = 0;
+  int device = 0;
+  bool f32 = false;
+  Launch cfg;
+  std::vector<LevelDev> lev;     // device views; rec/rhs/x hold byte offsets until bound
+  std::vector<size_t> rec_off, rhs_off, x_off;
+  size_t factor_bytes = 0, workspace_bytes = 0;
+  size_t buf_off[2] = {0, 0}, dwp_off = 0, info_off = 0;
+  void* meta = nullptr;          // device metadata (chunk_inst, chunk_off, node_off of every level)
+  // launch tracing (smnn_trace_enable); mutable: recorded during const calls
+  mutable std::vector<hipEvent_t> ev;
+  mutable std::vector<smnn_trace_record> rec;
+  mutable size_t used = 0;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int default_chunk(int K) {
+  switch (K) {
+    case 2: return 16;
+    case 3: return 8;
+    case 4: return 4;
+    default: return 4;
+  }
+}
+
+struct Bound {
+  std::vector<LevelDev> lev;
+  void* buf[2];
+  double* dwp;
+  uint32_t* info;
+};
+
+Bound bind(const smnn_plan* p, void* factor, void* workspace) {
+  Bound b;
+  b.lev = p->lev;
+  char* f = static_cast<char*>(factor);
+  char* ws = static_cast<char*>(workspace);
+  for (size_t l = 1; l < b.lev.size(); ++l) {
+    b.lev[l].rec = reinterpret_cast<double*>(f + p->rec_off[l]);
+    b.lev[l].rhs = reinterpret_cast<double*>(ws + p->rhs_off[l]);
+    b.lev[l].x = reinterpret_cast<double*>(ws + p->x_off[l]);
+  }
+  b.buf[0] = ws + p->buf_off[0];
+  b.buf[1] = ws + p->buf_off[1];
+  b.dwp = reinterpret_cast<double*>(ws + p->dwp_off);
+  b.info = reinterpret_cast<uint32_t*>(ws + p->info_off);
+  return b;
+}
+
+#define SMNN_HIP(call)                          \
+  do {                                          \
+    if ((call) != hipSuccess) return SMNN_ERR_HIP; \
+  } while (0)
+
+// Launch tracing: an event pair around every launch while enabled.
+struct Tracer {
+  const smnn_plan* p;
+  hipStream_t st;
+  bool on(int kernel, int level, int rhs, int out) const {
+    if (p->used >= p->rec.size()) return false;
+    smnn_trace_record& r = p->rec[p->used];
+    r.kernel = kernel; r.level = level; r.rhs = rhs; r.out = out; r.ms = 0.f;
+    return hipEventRecord(p->ev[2 * p->used], st) == hipSuccess;
+  }
+  void off() const {
+    (void)hipEventRecord(p->ev[2 * p->used + 1], st);
+    ++p->used;
+  }
+};
+
+#define SMNN_LAUNCH(TR, KIND, LEVEL, RHS, OUT, CALL)        \
+  do {                                                      \
+    const bool traced_ = (TR).on(KIND, LEVEL, RHS, OUT);    \
+    const hipError_t e_ = (CALL);                           \
+    if (traced_) (TR).off();                                \
+    if (e_ != hipSuccess) return SMNN_ERR_HIP;              \
+  } while (0)
+
+// One solve of M x = f through every level.  rhs selects f; the level-0
+// back-substitution writes `a.out` (OUT_STORE) or the gradients (OUT_GRAD).
+smnn_status solve(const smnn_plan* p, const Bound& b, int rhs, bool write_rec, int out_mode,
+                  const Level0Args& a, hipStream_t st) {
+  const int nl = static_cast<int>(b.lev.size());
+  const Tracer tr{p, st};
+  if (nl > 1)
+    SMNN_LAUNCH(tr, SMNN_K_REDUCE0, 0, rhs, 0,
+                launch_reduce0(p->K, p->L, p->f32, rhs, write_rec, b.lev[0], b.lev[1], a, p->cfg, st));
+  for (int l = 1; l + 1 < nl; ++l)
+    SMNN_LAUNCH(tr, SMNN_K_REDUCEN, l, rhs, 0,
+                launch_reduceN(p->K, p->L, write_rec, l, b.lev[l], b.lev[l + 1], a, p->cfg, st));
+  for (int l = nl - 1; l >= 1; --l)
+    SMNN_LAUNCH(tr, SMNN_K_BACKSUBN, l, rhs, 0,
+                launch_backsubN(p->K, p->L, l, b.lev[l], l + 1 < nl ? &b.lev[l + 1] : nullptr, a, p->cfg, st));
+  SMNN_LAUNCH(tr, SMNN_K_BACKSUB0, 0, rhs, out_mode,
+              launch_backsub0(p->K, p->L, p->f32, rhs, out_mode, b.lev[0], nl > 1 ? &b.lev[1] : nullptr, a,
+                              p->cfg, st));
+  return SMNN_OK;
+}
+
+smnn_status check_device(const smnn_plan* p) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return SMNN_ERR_HIP;
+  return dev == p->device ? SMNN_OK : SMNN_ERR_DEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
+  if (!out) return SMNN_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!d) return SMNN_ERR_INVALID_ARG;
+  if (d->order < 1 || d->order > 4) return SMNN_ERR_INVALID_ARG;
+  if (d->n_init < 0 || d->n_init > d->order + 1) return SMNN_ERR_INVALID_ARG;
+  if (d->n_inst < 1 || d->n_inst > INT32_MAX) return SMNN_ERR_INVALID_ARG;
+  if (d->mode < SMNN_MODE_FP64 || d->mode > SMNN_MODE_FP32_REFINED) return SMNN_ERR_INVALID_ARG;
+  if (d->refine_steps < -1 || d->refine_steps > 2) return SMNN_ERR_INVALID_ARG;
+  if (d->block < 0 || d->block > 256 || d->block % 64 != 0) return SMNN_ERR_INVALID_ARG;
+  if (d->max_blocks < 0) return SMNN_ERR_INVALID_ARG;
+  const int K = d->order + 1;
+  const int L = d->chunk ? d->chunk : default_chunk(K);
+  if (!supported(K, L)) return SMNN_ERR_UNSUPPORTED;
+  std::vector<int64_t> T(static_cast<size_t>(d->n_inst));
+  for (int64_t i = 0; i < d->n_inst; ++i) {
+    T[i] = d->steps ? d->steps[i] : d->steps_uniform;
+    if (T[i] < 1 || T[i] > (int64_t(1) << 40)) return SMNN_ERR_INVALID_ARG;
+  }
+
+  smnn_plan* p = new (std::nothrow) smnn_plan;
+  if (!p) return SMNN_ERR_HIP;
+  p->R = d->order;
+  p->K = K;
+  p->n_init = d->n_init;
+  p->mode = d->mode;
+  p->refine = d->mode == SMNN_MODE_FP64 ? 0 : (d->refine_steps < 0 ? 1 : d->refine_steps);
+  p->L = L;
+  p->N = d->n_inst;
+  p->f32 = d->mode == SMNN_MODE_FP32_REFINED;
+  p->cfg.block = d->block ? d->block : 256;
+  p->cfg.max_blocks = d->max_blocks;
+  if (hipGetDevice(&p->device) != hipSuccess) { delete p; return SMNN_ERR_HIP; }
+
+  std::vector<Level> lv = build_levels(T, L);
+  p->S = lv[0].nodes;
+  const int Q = K * (K + 1) / 2, REC = Q + K * K;
+  const size_t io = p->f32 ? sizeof(float) : sizeof(double);
+
+  // factor: level >= 1 node records
+  size_t fb = 0;
+  p->rec_off.assign(lv.size(), 0);
+  for (size_t l = 1; l < lv.size(); ++l) {
+    p->rec_off[l] = fb;
+    fb = align_up(fb + sizeof(double) * REC * lv[l].nodes);
+  }
+  // workspace: level >= 1 rhs and solution, two iterate buffers, chunk partials, info
+  size_t wb = 0;
+  p->rhs_off.assign(lv.size(), 0);
+  p->x_off.assign(lv.size(), 0);
+  for (size_t l = 1; l < lv.size(); ++l) {
+    p->rhs_off[l] = wb;
+    wb = align_up(wb + sizeof(double) * K * lv[l].nodes);
+    p->x_off[l] = wb;
+    wb = align_up(wb + sizeof(double) * K * lv[l].nodes);
+  }
+  const int nbuf = std::min(p->refine, 2);
+  for (int q = 0; q < 2; ++q) {
+    p->buf_off[q] = wb;
+    if (q < nbuf) wb = align_up(wb + io * K * p->S);
+  }
+  p->dwp_off = wb;
+  wb = align_up(wb + sizeof(double) * 3 * lv[0].chunks);
+  p->info_off = wb;
+  wb = align_up(wb + sizeof(uint32_t) * p->N);
+  p->factor_bytes = std::max<size_t>(fb, kAlign);
+  p->workspace_bytes = wb;
+
+  // device metadata
+  size_t mb = 0;
+  std::vector<size_t> ci(lv.size()), co(lv.size()), no(lv.size());
+  for (size_t l = 0; l < lv.size(); ++l) {
+    co[l] = mb; mb = align_up(mb + sizeof(int64_t) * (p->N + 1));
+    no[l] = mb; mb = align_up(mb + sizeof(int64_t) * (p->N + 1));
+    ci[l] = mb; mb = align_up(mb + sizeof(int32_t) * std::max<int64_t>(lv[l].chunks, 1));
+  }
+  std::vector<char> host(mb, 0);
+  for (size_t l = 0; l < lv.size(); ++l) {
+    std::copy(lv[l].chunk_off.begin(), lv[l].chunk_off.end(), reinterpret_cast<int64_t*>(host.data() + co[l]));
+    std::copy(lv[l].node_off.begin(), lv[l].node_off.end(), reinterpret_cast<int64_t*>(host.data() + no[l]));
+    std::copy(lv[l].chunk_inst.begin(), lv[l].chunk_inst.end(), reinterpret_cast<int32_t*>(host.data() + ci[l]));
+  }
+  if (hipMalloc(&p->meta, mb) != hipSuccess) { delete p; return SMNN_ERR_HIP; }
+  if (hipMemcpy(p->meta, host.data(), mb, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(p->meta);
+    delete p;
+    return SMNN_ERR_HIP;
+  }
+  char* m = static_cast<char*>(p->meta);
+  p->lev.resize(lv.size());
+  for (size_t l = 0; l < lv.size(); ++l) {
+    p->lev[l].chunk_inst = reinterpret_cast<const int32_t*>(m + ci[l]);
+    p->lev[l].chunk_off = reinterpret_cast<const int64_t*>(m + co[l]);
+    p->lev[l].node_off = reinterpret_cast<const int64_t*>(m + no[l]);
+    p->lev[l].chunks = lv[l].chunks;
+    p->lev[l].nodes = lv[l].nodes;
+  }
+  *out = p;
+  return SMNN_OK;
+}
+
+smnn_status smnn_trace_enable(smnn_plan* p, int32_t capacity) {
+  if (!p || capacity < 0) return SMNN_ERR_INVALID_ARG;
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  p->ev.clear();
+  p->rec.clear();
+  p->used = 0;
+  if (capacity == 0) return SMNN_OK;
+  p->ev.resize(2 * static_cast<size_t>(capacity), nullptr);
+  for (auto& e : p->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      smnn_trace_enable(p, 0);
+      return SMNN_ERR_HIP;
+    }
+  p->rec.resize(capacity);
+  return SMNN_OK;
+}
+
+int32_t smnn_trace_read(smnn_plan* p, smnn_trace_record* out, int32_t cap) {
+  if (!p || (!out && cap > 0)) return -1;
+  int32_t n = 0;
+  for (size_t i = 0; i < p->used && n < cap; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]) != hipSuccess) return -1;
+    out[n] = p->rec[i];
+    out[n].ms = ms;
+    ++n;
+  }
+  p->used = 0;
+  return n;
+}
+
+smnn_status smnn_plan_destroy(smnn_plan* p) {
+  if (!p) return SMNN_ERR_INVALID_ARG;
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  if (p->meta) (void)hipFree(p->meta);
+  delete p;
+  return SMNN_OK;
+}
+
+smnn_status smnn_plan_sizes(const smnn_plan* p, size_t* factor_bytes, size_t* workspace_bytes,
+                            int64_t* total_steps) {
+  if (!p) return SMNN_ERR_INVALID_ARG;
+  if (factor_bytes) *factor_bytes = p->factor_bytes;
+  if (workspace_bytes) *workspace_bytes = p->workspace_bytes;
+  if (total_steps) *total_steps = p->S;
+  return SMNN_OK;
+}
+
+int64_t smnn_plan_query(const smnn_plan* p, int32_t key) {
+  if (!p) return -1;
+  if (key == SMNN_Q_LEVELS) return static_cast<int64_t>(p->lev.size());
+  if (key == SMNN_Q_CHUNK) return p->L;
+  if (key == SMNN_Q_REFINE) return p->refine;
+  if (key == SMNN_Q_MODE) return p->mode;
+  if (key >= 1000 && key < 1000 + static_cast<int32_t>(p->lev.size())) return p->lev[key - 1000].nodes;
+  if (key >= 2000 && key < 2000 + static_cast<int32_t>(p->lev.size())) return p->lev[key - 2000].chunks;
+  return -1;
+}
+
+smnn_status smnn_forward(const smnn_plan* p, const void* c, const void* b, const void* h, const void* u0,
+                         const void* w, void* y, void* factor, size_t factor_bytes, void* workspace,
+                         size_t workspace_bytes, int32_t* info, void* stream) {
+  if (!p || !c || !b || !h || !w || !y || !factor || !workspace) return SMNN_ERR_INVALID_ARG;
+  if (factor_bytes < p->factor_bytes || workspace_bytes < p->workspace_bytes) return SMNN_ERR_WORKSPACE;
+  if (p->n_init > 0 && !u0) return SMNN_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(factor) | reinterpret_cast<uintptr_t>(workspace)) % kAlign)
+    return SMNN_ERR_INVALID_ARG;
+  const smnn_status ds = check_device(p);
+  if (ds != SMNN_OK) return ds;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Bound bd = bind(p, factor, workspace);
+  Level0Args a;
+  a.c = c; a.d = b; a.s = h; a.u0 = u0; a.w = w;
+  a.n_init = p->n_init;
+  a.N = p->N;
+  a.info = info ? bd.info : nullptr;
+  SMNN_HIP(launch_info_init(a, st));
+  a.out = p->refine == 0 ? y : bd.buf[0];
+  smnn_status s = solve(p, bd, RHS_BETA, true, OUT_STORE, a, st);
+  if (s != SMNN_OK) return s;
+  for (int m = 1; m <= p->refine; ++m) {
+    a.v = a.out;
+    a.out = (m == p->refine) ? y : bd.buf[m % 2];
+    s = solve(p, bd, RHS_RESID, false, OUT_STORE, a, st);
+    if (s != SMNN_OK) return s;
+  }
+  SMNN_HIP(launch_info_finalize(a, info, st));
+  return SMNN_OK;
+}
+
+smnn_status smnn_backward(const smnn_plan* p, const void* c, const void* b, const void* h, const void* u0,
+                          const void* w, const void* y, const void* factor, size_t factor_bytes, const void* gy,
+                          void* dc, void* db, void* dh, void* du0, void* dw, void* workspace,
+                          size_t workspace_bytes, int32_t* info, void* stream) {
+  if (!p || !c || !b || !h || !w || !y || !factor || !gy || !dc || !db || !dh || !dw || !workspace)
+    return SMNN_ERR_INVALID_ARG;
+  if (factor_bytes < p->factor_bytes || workspace_bytes < p->workspace_bytes) return SMNN_ERR_WORKSPACE;
+  if (p->n_init > 0 && (!u0 || !du0)) return SMNN_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(factor) | reinterpret_cast<uintptr_t>(workspace)) % kAlign)
+    return SMNN_ERR_INVALID_ARG;
+  const smnn_status ds = check_device(p);
+  if (ds != SMNN_OK) return ds;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Bound bd = bind(p, const_cast<void*>(factor), workspace);
+  Level0Args a;
+  a.c = c; a.d = b; a.s = h; a.u0 = u0; a.w = w; a.g = gy; a.y = y;
+  a.dc = dc; a.dd = db; a.ds = dh; a.du0 = du0; a.dw = dw; a.dw_part = bd.dwp;
+  a.n_init = p->n_init;
+  a.N = p->N;
+  a.info = info ? bd.info : nullptr;
+  SMNN_HIP(launch_info_init(a, st));
+  smnn_status s;
+  if (p->refine == 0) {
+    s = solve(p, bd, RHS_G, false, OUT_GRAD, a, st);
+    if (s != SMNN_OK) return s;
+  } else {
+    a.out = bd.buf[0];
+    s = solve(p, bd, RHS_G, false, OUT_STORE, a, st);
+    if (s != SMNN_OK) return s;
+    for (int m = 1; m <= p->refine; ++m) {
+      a.v = a.out;
+      const bool lastm = m == p->refine;
+      a.out = lastm ? nullptr : bd.buf[m % 2];
+      s = solve(p, bd, RHS_GRESID, false, lastm ? OUT_GRAD : OUT_STORE, a, st);
+      if (s != SMNN_OK) return s;
+    }
+  }
+  const Tracer tr{p, st};
+  SMNN_LAUNCH(tr, SMNN_K_DW, 0, 0, 0, launch_dw_reduce(p->f32, bd.lev[0], a, st));
+  SMNN_HIP(launch_info_finalize(a, info, st));
+  return SMNN_OK;
+}
+
+const char* smnn_status_string(smnn_status s) {
+  switch (s) {
+    case SMNN_OK: return "ok";
+    case SMNN_ERR_INVALID_ARG: return "invalid argument";
+    case SMNN_ERR_UNSUPPORTED: return "unsupported order or chunk length";
+    case SMNN_ERR_WORKSPACE: return "workspace or factor too small";
+    case SMNN_ERR_HIP: return "HIP runtime error";
+    case SMNN_ERR_DEVICE: return "current device differs from the plan's device";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

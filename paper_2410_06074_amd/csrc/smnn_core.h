@@ -1,0 +1,718 @@
+// Per-lane arithmetic of the batched S-MNN least-squares solve.
+//
+// Everything here is a pure function of register arrays, usable from HIP
+// device code (the kernels in smnn_kernels.hip) and from host code (the
+// indexing checker in tests/emu).  Notation follows the paper
+// (Scalable Mechanistic Neural Networks):
+//   * one instance = one (batch, variable) pair: V = Q = 1, T_init = 1,
+//     block size K = R + 1;
+//   * node t carries the unknowns y_t (K values);
+//   * M is block tridiagonal (Eq. 10): diagonal blocks A_t ("M_t"),
+//     block (t+1, t) = B_t ("N_t"), right-hand side f_t ("beta_t");
+//   * the blocks come from App. A.2: governing term w_g^2 c_t c_t^T, initial
+//     term w_i^2 U, and the smoothness terms of the rows of Eqs. 6-7
+//     weighted by w_s s_t^r (the weighting before Eq. 9).
+//
+// Elimination follows the block Cholesky recurrence of Alg. 3 and the
+// substitutions of Alg. 4 (Cholesky form, Eqs. 11-13) inside a chunk of
+// consecutive nodes; chunks are coupled through separator nodes whose Schur
+// complement is again block tridiagonal (see smnn_kernels.hip).
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define SMNN_HD __host__ __device__ __forceinline__
+#else
+#define SMNN_HD inline
+#endif
+
+namespace smnn {
+
+template <int K>
+struct Dim {
+  static constexpr int Q = K * (K + 1) / 2;  // packed lower triangle
+  static constexpr int KK = K * K;
+  static constexpr int P = 2 * K - 1;        // powers s^0 .. s^{2R}
+};
+
+SMNN_HD constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// Compile-time coefficients of the smoothness blocks.  With S+ = diag(s^r),
+// F_{ij} = 1/(j-i)! (j >= i) as in App. A.2, every entry of the three blocks
+// a pair of neighbouring nodes contributes is w_s^2 s^{i+j} times a constant:
+//   left node  (S+ F^T F S+ + S^2)_{ij}      = s^{i+j} (alpha_ij + [i=j])
+//   right node (S- F^T F S- + S^2)_{ij}      = s^{i+j} ((-1)^{i+j} alpha_ij + [i=j])
+//   coupling   (-S+ F S+ - S- F^T S-)_{ij}   = s^{i+j} nu_ij      (block (t+1, t))
+// alpha_ij = sum_{r <= min(i,j)} 1/((i-r)!(j-r)!),
+// nu_ij    = -([j >= i]/(j-i)! + [i >= j] (-1)^{i-j}/(i-j)!).
+template <int K>
+struct Coef {
+  double inv_fact[K];
+  double alpha[K][K];
+  double nu[K][K];
+  constexpr Coef() : inv_fact(), alpha(), nu() {
+    double f = 1.0;
+    for (int n = 0; n < K; ++n) {
+      if (n > 0) f *= n;
+      inv_fact[n] = 1.0 / f;
+    }
+    for (int i = 0; i < K; ++i)
+      for (int j = 0; j < K; ++j) {
+        double s = 0.0;
+        const int m = i < j ? i : j;
+        for (int r = 0; r <= m; ++r) s += inv_fact[i - r] * inv_fact[j - r];
+        alpha[i][j] = s;
+        double v = 0.0;
+        if (j >= i) v += inv_fact[j - i];
+        if (i >= j) v += (((i - j) & 1) ? -1.0 : 1.0) * inv_fact[i - j];
+        nu[i][j] = -v;
+      }
+  }
+};
+
+// ---------------------------------------------------------------- algebra
+// In-place Cholesky of the packed symmetric matrix D.  On return the strict
+// lower part holds L and the diagonal holds 1/L_jj.  Returns false when a
+// pivot is not > 0 (or is NaN); the NaN then propagates to the results.
+template <int K>
+SMNN_HD bool chol(double (&D)[Dim<K>::Q]) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    double d = D[tri(j, j)];
+#pragma unroll
+    for (int m = 0; m < j; ++m) d -= D[tri(j, m)] * D[tri(j, m)];
+    ok = ok && (d > 0.0);
+    const double inv = 1.0 / sqrt(d);
+    D[tri(j, j)] = inv;
+#pragma unroll
+    for (int i = j + 1; i < K; ++i) {
+      double v = D[tri(i, j)];
+#pragma unroll
+      for (int m = 0; m < j; ++m) v -= D[tri(i, m)] * D[tri(j, m)];
+      D[tri(i, j)] = v * inv;
+    }
+  }
+  return ok;
+}
+
+// v <- L^{-1} v
+template <int K>
+SMNN_HD void lsolve(const double (&L)[Dim<K>::Q], double (&v)[K]) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    double t = v[j];
+#pragma unroll
+    for (int m = 0; m < j; ++m) t -= L[tri(j, m)] * v[m];
+    v[j] = t * L[tri(j, j)];
+  }
+}
+
+// v <- L^{-T} v
+template <int K>
+SMNN_HD void usolve(const double (&L)[Dim<K>::Q], double (&v)[K]) {
+#pragma unroll
+  for (int j = K - 1; j >= 0; --j) {
+    double t = v[j];
+#pragma unroll
+    for (int m = j + 1; m < K; ++m) t -= L[tri(m, j)] * v[m];
+    v[j] = t * L[tri(j, j)];
+  }
+}
+
+// W <- W L^{-T}   (W row-major K x K)
+template <int K>
+SMNN_HD void rsolve_t(const double (&L)[Dim<K>::Q], double (&W)[Dim<K>::KK]) {
+#pragma unroll
+  for (int r = 0; r < K; ++r)
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      double t = W[r * K + j];
+#pragma unroll
+      for (int m = 0; m < j; ++m) t -= W[r * K + m] * L[tri(j, m)];
+      W[r * K + j] = t * L[tri(j, j)];
+    }
+}
+
+// X <- L^{-1} X   (column by column)
+template <int K>
+SMNN_HD void lsolve_cols(const double (&L)[Dim<K>::Q], double (&X)[Dim<K>::KK]) {
+#pragma unroll
+  for (int c = 0; c < K; ++c)
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      double t = X[j * K + c];
+#pragma unroll
+      for (int m = 0; m < j; ++m) t -= L[tri(j, m)] * X[m * K + c];
+      X[j * K + c] = t * L[tri(j, j)];
+    }
+}
+
+// D <- A - W W^T  (packed lower)
+template <int K>
+SMNN_HD void sym_minus_wwt(const double (&A)[Dim<K>::Q], const double (&W)[Dim<K>::KK],
+                           double (&D)[Dim<K>::Q]) {
+#pragma unroll
+  for (int i = 0; i < K; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      double t = A[tri(i, j)];
+#pragma unroll
+      for (int m = 0; m < K; ++m) t -= W[i * K + m] * W[j * K + m];
+      D[tri(i, j)] = t;
+    }
+}
+
+// y <- y - W x
+template <int K>
+SMNN_HD void sub_matvec(const double (&W)[Dim<K>::KK], const double (&x)[K], double (&y)[K]) {
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    double t = y[i];
+#pragma unroll
+    for (int m = 0; m < K; ++m) t -= W[i * K + m] * x[m];
+    y[i] = t;
+  }
+}
+
+// y <- y - B^T x
+template <int K>
+SMNN_HD void sub_matvec_t(const double (&B)[Dim<K>::KK], const double (&x)[K], double (&y)[K]) {
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    double t = y[i];
+#pragma unroll
+    for (int m = 0; m < K; ++m) t -= B[m * K + i] * x[m];
+    y[i] = t;
+  }
+}
+
+// Z <- -W X
+template <int K>
+SMNN_HD void neg_matmul(const double (&W)[Dim<K>::KK], const double (&X)[Dim<K>::KK],
+                        double (&Z)[Dim<K>::KK]) {
+#pragma unroll
+  for (int i = 0; i < K; ++i)
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      double t = 0.0;
+#pragma unroll
+      for (int m = 0; m < K; ++m) t -= W[i * K + m] * X[m * K + j];
+      Z[i * K + j] = t;
+    }
+}
+
+// S += X^T X (packed), r += X^T g
+template <int K>
+SMNN_HD void acc_xtx(const double (&X)[Dim<K>::KK], const double (&g)[K], double (&S)[Dim<K>::Q],
+                     double (&r)[K]) {
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      double t = S[tri(i, j)];
+#pragma unroll
+      for (int m = 0; m < K; ++m) t += X[m * K + i] * X[m * K + j];
+      S[tri(i, j)] = t;
+    }
+    double t = r[i];
+#pragma unroll
+    for (int m = 0; m < K; ++m) t += X[m * K + i] * g[m];
+    r[i] = t;
+  }
+}
+
+// ------------------------------------------------------- smoothness blocks
+template <int K>
+SMNN_HD void powers(double s, double (&pw)[Dim<K>::P]) {
+  pw[0] = 1.0;
+#pragma unroll
+  for (int e = 1; e < Dim<K>::P; ++e) pw[e] = pw[e - 1] * s;
+}
+
+// A += w_s^2 * (smoothness block of the LEFT node of a pair with step s)
+template <int K>
+SMNN_HD void add_left_block(const double (&pw)[Dim<K>::P], double ws2, double (&A)[Dim<K>::Q]) {
+  constexpr Coef<K> C{};
+#pragma unroll
+  for (int i = 0; i < K; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j)
+      A[tri(i, j)] += ws2 * pw[i + j] * (C.alpha[i][j] + (i == j ? 1.0 : 0.0));
+}
+
+// A += w_s^2 * (smoothness block of the RIGHT node of a pair with step s)
+template <int K>
+SMNN_HD void add_right_block(const double (&pw)[Dim<K>::P], double ws2, double (&A)[Dim<K>::Q]) {
+  constexpr Coef<K> C{};
+#pragma unroll
+  for (int i = 0; i < K; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j)
+      A[tri(i, j)] += ws2 * pw[i + j] *
+                      ((((i + j) & 1) ? -C.alpha[i][j] : C.alpha[i][j]) + (i == j ? 1.0 : 0.0));
+}
+
+// B = w_s^2 * coupling block (row = right node, column = left node)
+template <int K>
+SMNN_HD void coupling_block(const double (&pw)[Dim<K>::P], double ws2, double (&B)[Dim<K>::KK]) {
+  constexpr Coef<K> C{};
+#pragma unroll
+  for (int i = 0; i < K; ++i)
+#pragma unroll
+    for (int j = 0; j < K; ++j) B[i * K + j] = ws2 * pw[i + j] * C.nu[i][j];
+}
+
+// Row residuals of the 2K weighted smoothness rows of a pair (Eqs. 6-7 scaled
+// by w_s s^r) at (v_t, v_{t+1}): rho = -(a . v); returns the contributions
+// a^T rho to the left node (cl) and to the right node (cr).
+template <int K>
+SMNN_HD void pair_residual(const double (&pw)[Dim<K>::P], double ws, const double (&vt)[K],
+                           const double (&vn)[K], double (&cl)[K], double (&cr)[K]) {
+  constexpr Coef<K> C{};
+#pragma unroll
+  for (int j = 0; j < K; ++j) { cl[j] = 0.0; cr[j] = 0.0; }
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    // forward row r: sum_{j>=r} w_s s^j/(j-r)! v_{t,j} - w_s s^r v_{t+1,r}
+    double af = -ws * pw[r] * vn[r];
+#pragma unroll
+    for (int j = r; j < K; ++j) af += ws * pw[j] * C.inv_fact[j - r] * vt[j];
+    const double rf = -af;
+    // backward row r: sum_{j>=r} w_s (-1)^{j-r} s^j/(j-r)! v_{t+1,j} - w_s s^r v_{t,r}
+    double ab = -ws * pw[r] * vt[r];
+#pragma unroll
+    for (int j = r; j < K; ++j)
+      ab += ws * pw[j] * (((j - r) & 1) ? -C.inv_fact[j - r] : C.inv_fact[j - r]) * vn[j];
+    const double rb = -ab;
+#pragma unroll
+    for (int j = r; j < K; ++j) {
+      cl[j] += ws * pw[j] * C.inv_fact[j - r] * rf;
+      cr[j] += ws * pw[j] * (((j - r) & 1) ? -C.inv_fact[j - r] : C.inv_fact[j - r]) * rb;
+    }
+    cr[r] += -ws * pw[r] * rf;
+    cl[r] += -ws * pw[r] * rb;
+  }
+}
+
+// Gradient contributions of the 2K smoothness rows of a pair.  For a weighted
+// row a~ (depends on s and w_s) with rho = a~.y and mu = a~.lam the loss
+// gradient is -( (da~.lam) rho + mu (da~.y) ) for s and -2 rho mu / w_s for
+// w_s.  Rows are evaluated without the w_s factor (hat) to avoid dividing.
+template <int K>
+SMNN_HD void pair_grad(double s, double ws, const double (&yt)[K], const double (&yn)[K],
+                       const double (&lt)[K], const double (&ln)[K], double& ds, double& dws) {
+  constexpr Coef<K> C{};
+  double pw[K];
+  pw[0] = 1.0;
+#pragma unroll
+  for (int e = 1; e < K; ++e) pw[e] = pw[e - 1] * s;
+  double acc_s = 0.0, acc_w = 0.0;
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    // forward row r
+    double rho = -pw[r] * yn[r], mu = -pw[r] * ln[r];
+    double dy = (r > 0) ? -r * pw[r - 1] * yn[r] : 0.0;
+    double dl = (r > 0) ? -r * pw[r - 1] * ln[r] : 0.0;
+#pragma unroll
+    for (int j = r; j < K; ++j) {
+      const double cf = C.inv_fact[j - r];
+      rho += pw[j] * cf * yt[j];
+      mu += pw[j] * cf * lt[j];
+      if (j > 0) {
+        dy += j * pw[j - 1] * cf * yt[j];
+        dl += j * pw[j - 1] * cf * lt[j];
+      }
+    }
+    acc_s += dl * rho + mu * dy;
+    acc_w += rho * mu;
+    // backward row r
+    rho = -pw[r] * yt[r];
+    mu = -pw[r] * lt[r];
+    dy = (r > 0) ? -r * pw[r - 1] * yt[r] : 0.0;
+    dl = (r > 0) ? -r * pw[r - 1] * lt[r] : 0.0;
+#pragma unroll
+    for (int j = r; j < K; ++j) {
+      const double cf = ((j - r) & 1) ? -C.inv_fact[j - r] : C.inv_fact[j - r];
+      rho += pw[j] * cf * yn[j];
+      mu += pw[j] * cf * ln[j];
+      if (j > 0) {
+        dy += j * pw[j - 1] * cf * yn[j];
+        dl += j * pw[j - 1] * cf * ln[j];
+      }
+    }
+    acc_s += dl * rho + mu * dy;
+    acc_w += rho * mu;
+  }
+  ds = -ws * ws * acc_s;
+  dws = -2.0 * ws * acc_w;
+}
+
+// Chunk geometry at one level.  Chunks have L nodes; chunk j of an instance
+// with n nodes owns nodes jL .. min(jL+L, n)-1.  Every chunk but the last
+// ends in a separator (its last owned node); the last chunk has no separator
+// and may hold up to L interior nodes.  n <= L gives a single chunk.
+struct ChunkGeom {
+  int64_t a, b;       // interior nodes a..b
+  bool has_left, has_right;
+};
+
+SMNN_HD ChunkGeom chunk_geom(int64_t j, int64_t n, int L) {
+  ChunkGeom g;
+  g.a = j * L;
+  const bool last = g.a + L >= n;
+  g.b = last ? n - 1 : g.a + L - 2;
+  g.has_left = j > 0;
+  g.has_right = !last;
+  return g;
+}
+
+// ------------------------------------------------------------ chunk cores
+// A chunk covers nodes a..b of one instance's block-tridiagonal system.  The
+// node at a-1 (if has_left) and b+1 (if has_right) are separators.  Src
+// supplies   load(i, A, f)   diagonal block and right-hand side of node i,
+//            coupling(i, B)  block (i+1, i).
+
+// Result of eliminating a chunk's interior (Schur complement pieces).
+template <int K>
+struct Reduced {
+  double rA[Dim<K>::Q];   // right separator: A_{b+1} - B_b D_b^{-1} B_b^T
+  double rf[K];           //                  f_{b+1} - B_b D_b^{-1} g_b
+  double lA[Dim<K>::Q];   // left separator contribution: -E_L^T A_I^{-1} E_L
+  double lf[K];           //                              -E_L^T A_I^{-1} f_I
+  double lB[Dim<K>::KK];  // coupling (b+1, a-1): -B_b [A_I^{-1}]_{b,a} B_{a-1}
+  int fail;               // chunk-relative node + 1 of the first non-positive pivot, 0 if none
+};
+
+template <int K, int L, class Src>
+SMNN_HD void reduce_chunk(const Src& src, int64_t a, int64_t b, bool has_left, bool has_right,
+                          Reduced<K>& out) {
+  constexpr int Q = Dim<K>::Q, KK = Dim<K>::KK;
+  double Lc[Q], gh[K], Xh[KK];
+#pragma unroll
+  for (int e = 0; e < Q; ++e) out.lA[e] = 0.0;
+#pragma unroll
+  for (int e = 0; e < K; ++e) out.lf[e] = 0.0;
+#pragma unroll
+  for (int e = 0; e < KK; ++e) { out.lB[e] = 0.0; Xh[e] = 0.0; }
+  out.fail = 0;
+#pragma unroll
+  for (int u = 0; u < L; ++u) {
+    const int64_t i = a + u;
+    if (i > b) break;
+    double A[Q], f[K];
+    src.load(i, A, f);
+    double D[Q], X[KK];
+    if (u == 0) {
+#pragma unroll
+      for (int e = 0; e < Q; ++e) D[e] = A[e];
+      if (has_left) src.coupling(a - 1, X);   // E_L block: (a, a-1) = B_{a-1}
+    } else {
+      double W[KK];
+      src.coupling(i - 1, W);
+      rsolve_t<K>(Lc, W);                      // W = B_{i-1} L_{i-1}^{-T}
+      sym_minus_wwt<K>(A, W, D);               // D_i = A_i - W W^T
+      sub_matvec<K>(W, gh, f);                 // g_i = f_i - W ghat_{i-1}
+      if (has_left) neg_matmul<K>(W, Xh, X);   // X_i = -W Xhat_{i-1}
+    }
+    const bool ok = chol<K>(D);
+    if (!ok && out.fail == 0) out.fail = u + 1;
+#pragma unroll
+    for (int e = 0; e < Q; ++e) Lc[e] = D[e];
+#pragma unroll
+    for (int e = 0; e < K; ++e) gh[e] = f[e];
+    lsolve<K>(Lc, gh);                         // ghat_i = L_i^{-1} g_i
+    if (has_left) {
+#pragma unroll
+      for (int e = 0; e < KK; ++e) Xh[e] = X[e];
+      lsolve_cols<K>(Lc, Xh);                  // Xhat_i = L_i^{-1} X_i
+      acc_xtx<K>(Xh, gh, out.lA, out.lf);      // sum Xhat^T Xhat, sum Xhat^T ghat
+    }
+  }
+  if (has_left) {
+#pragma unroll
+    for (int e = 0; e < Q; ++e) out.lA[e] = -out.lA[e];
+#pragma unroll
+    for (int e = 0; e < K; ++e) out.lf[e] = -out.lf[e];
+  }
+  if (has_right) {
+    double V[KK];
+    src.coupling(b, V);
+    rsolve_t<K>(Lc, V);                        // V = B_b L_b^{-T}
+    double A[Q], f[K];
+    src.load(b + 1, A, f);
+    sym_minus_wwt<K>(A, V, out.rA);
+    sub_matvec<K>(V, gh, f);
+#pragma unroll
+    for (int e = 0; e < K; ++e) out.rf[e] = f[e];
+    if (has_left) neg_matmul<K>(V, Xh, out.lB);
+  }
+}
+
+// Solve the chunk interior a..b with the separator values xl (node a-1) and
+// xr (node b+1) known.  x[u] receives node a+u for u = 0..b-a (it first holds
+// the forward-substituted right-hand sides, then the solution).
+template <int K, int L, class Src>
+SMNN_HD int backsub_chunk(const Src& src, int64_t a, int64_t b, bool has_left, bool has_right,
+                          const double (&xl)[K], const double (&xr)[K], double (&x)[L][K]) {
+  constexpr int Q = Dim<K>::Q, KK = Dim<K>::KK;
+  double Ls[L][Q];
+  int fail = 0;
+#pragma unroll
+  for (int u = 0; u < L; ++u) {
+    const int64_t i = a + u;
+    if (i > b) break;
+    double A[Q], f[K];
+    src.load(i, A, f);
+    if (u == 0 && has_left) {
+      double B[KK];
+      src.coupling(a - 1, B);
+      sub_matvec<K>(B, xl, f);                 // f_a -= B_{a-1} x_{a-1}
+    }
+    if (i == b && has_right) {
+      double B[KK];
+      src.coupling(b, B);
+      sub_matvec_t<K>(B, xr, f);               // f_b -= B_b^T x_{b+1}
+    }
+    double D[Q];
+    if (u == 0) {
+#pragma unroll
+      for (int e = 0; e < Q; ++e) D[e] = A[e];
+    } else {
+      double W[KK];
+      src.coupling(i - 1, W);
+      rsolve_t<K>(Ls[u > 0 ? u - 1 : 0], W);   // W = B_{i-1} L_{i-1}^{-T}
+      sym_minus_wwt<K>(A, W, D);               // D_i = A_i - W W^T
+      sub_matvec<K>(W, x[u > 0 ? u - 1 : 0], f);
+    }
+    const bool ok = chol<K>(D);
+    if (!ok && fail == 0) fail = u + 1;
+#pragma unroll
+    for (int e = 0; e < Q; ++e) Ls[u][e] = D[e];
+    lsolve<K>(Ls[u], f);                       // ghat_i = L_i^{-1} g_i
+#pragma unroll
+    for (int e = 0; e < K; ++e) x[u][e] = f[e];
+  }
+#pragma unroll
+  for (int u = L - 1; u >= 0; --u) {
+    const int64_t i = a + u;
+    if (i > b) continue;
+    if (i < b) {
+      double B[KK], t[K];
+      src.coupling(i, B);
+#pragma unroll
+      for (int e = 0; e < K; ++e) t[e] = 0.0;
+      sub_matvec_t<K>(B, x[u + 1 < L ? u + 1 : u], t);   // t = -B_i^T x_{i+1}
+      lsolve<K>(Ls[u], t);
+#pragma unroll
+      for (int e = 0; e < K; ++e) x[u][e] += t[e];
+    }
+    usolve<K>(Ls[u], x[u]);                    // x_i = L^{-T}(ghat_i - L^{-1} B_i^T x_{i+1})
+  }
+  return fail;
+}
+
+// ----------------------------------------------------------- level-0 source
+// Per-instance parameters: weights (unsquared) and initial values.
+template <int K>
+struct Inst {
+  double wg, wi, ws;
+  double u0[K];
+  int n_init;
+};
+
+enum RhsMode : int {
+  RHS_BETA = 0,   // f = beta (Eq. 9's A^T W b, App. A.2)
+  RHS_RESID = 1,  // f = A^T W (b - A v)         (refinement of the solution)
+  RHS_G = 2,      // f = g = dl/dy                (adjoint, Eq. 14)
+  RHS_GRESID = 3  // f = g - A^T W A v            (refinement of the adjoint)
+};
+
+// Node data assembled on the fly from the per-step inputs of one instance.
+// TIO is the element type of the arrays in memory (double or float).
+template <int K, class TIO, int RHS>
+struct Src0 {
+  const TIO* c;      // [n][K] of this instance
+  const TIO* d;      // [n]
+  const TIO* s;      // [n]  (s[n-1] unused)
+  const TIO* g;      // [n][K]  dl/dy (RHS_G, RHS_GRESID)
+  const TIO* v;      // [n][K]  previous iterate (RHS_RESID, RHS_GRESID)
+  int64_t n;
+  Inst<K> p;
+
+  SMNN_HD double ld(const TIO* ptr, int64_t idx) const { return static_cast<double>(ptr[idx]); }
+
+  SMNN_HD void coupling(int64_t i, double (&B)[Dim<K>::KK]) const {
+    double pw[Dim<K>::P];
+    powers<K>(ld(s, i), pw);
+    coupling_block<K>(pw, p.ws * p.ws, B);
+  }
+
+  SMNN_HD void load(int64_t i, double (&A)[Dim<K>::Q], double (&f)[K]) const {
+    double ci[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) ci[r] = ld(c, i * K + r);
+    const double wg2 = p.wg * p.wg, wi2 = p.wi * p.wi, ws2 = p.ws * p.ws;
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+#pragma unroll
+      for (int q = 0; q <= r; ++q) A[tri(r, q)] = wg2 * ci[r] * ci[q];
+    if (i == 0) {
+#pragma unroll
+      for (int r = 0; r < K; ++r)
+        if (r < p.n_init) A[tri(r, r)] += wi2;
+    }
+    double pl[Dim<K>::P], pr[Dim<K>::P];
+    const bool has_next = i + 1 < n, has_prev = i > 0;
+    if (has_next) {
+      powers<K>(ld(s, i), pr);
+      add_left_block<K>(pr, ws2, A);
+    }
+    if (has_prev) {
+      powers<K>(ld(s, i - 1), pl);
+      add_right_block<K>(pl, ws2, A);
+    }
+    if (RHS == RHS_BETA) {
+      const double di = ld(d, i);
+#pragma unroll
+      for (int r = 0; r < K; ++r) f[r] = wg2 * ci[r] * di;
+      if (i == 0) {
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+          if (r < p.n_init) f[r] += wi2 * p.u0[r];
+      }
+    } else if (RHS == RHS_G) {
+#pragma unroll
+      for (int r = 0; r < K; ++r) f[r] = ld(g, i * K + r);
+    } else {
+      // residual A^T W (b - A v) row by row; b = 0 for the adjoint (RHS_GRESID)
+      double vi[K];
+#pragma unroll
+      for (int r = 0; r < K; ++r) vi[r] = ld(v, i * K + r);
+      double e = (RHS == RHS_RESID) ? ld(d, i) : 0.0;
+#pragma unroll
+      for (int r = 0; r < K; ++r) e -= ci[r] * vi[r];
+#pragma unroll
+      for (int r = 0; r < K; ++r) f[r] = (RHS == RHS_GRESID ? ld(g, i * K + r) : 0.0) + wg2 * ci[r] * e;
+      if (i == 0) {
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+          if (r < p.n_init) f[r] += wi2 * ((RHS == RHS_RESID ? p.u0[r] : 0.0) - vi[r]);
+      }
+      if (has_next) {
+        double vn[K], cl[K], cr[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r) vn[r] = ld(v, (i + 1) * K + r);
+        pair_residual<K>(pr, p.ws, vi, vn, cl, cr);
+#pragma unroll
+        for (int r = 0; r < K; ++r) f[r] += cl[r];
+      }
+      if (has_prev) {
+        double vp[K], cl[K], cr[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r) vp[r] = ld(v, (i - 1) * K + r);
+        pair_residual<K>(pl, p.ws, vp, vi, cl, cr);
+#pragma unroll
+        for (int r = 0; r < K; ++r) f[r] += cr[r];
+      }
+    }
+  }
+};
+
+// Parameter gradients of the rows owned by one chunk (level 0).  lam and y
+// hold nodes a-1 .. last (index 0 = node a-1) with last = b+1 when the chunk
+// has a right separator, else b.  Per weighted row a~ . y = b~ with
+// rho = a~.y - b~ and mu = a~.lam, dl/dtheta = -[(da~.lam) rho + mu (da~.y - db~)]
+// (Eq. 14 chained through the row).  The chunk owns the governing rows of its
+// nodes a..last, the initial rows when a = 0, and the smoothness pairs
+// (t, t+1) for t = a-1 .. last-1.  dw receives this chunk's partial sums.
+template <int K, int L, class TIO>
+SMNN_HD void grad_chunk(const TIO* c, const TIO* d, const TIO* s, int64_t n, const Inst<K>& p,
+                        const ChunkGeom& G, const double (&lam)[L + 1][K], const double (&y)[L + 1][K],
+                        TIO* dc, TIO* dd, TIO* ds, TIO* du0, double (&dw)[3]) {
+  const int64_t a = G.a;
+  const int64_t last = G.has_right ? G.b + 1 : G.b;
+  const double wg2 = p.wg * p.wg, wi2 = p.wi * p.wi;
+  double dwg = 0.0, dwi = 0.0, dws = 0.0;
+#pragma unroll
+  for (int u = 0; u < L; ++u) {
+    const int64_t t = a + u;
+    if (t > last) break;
+    double e = -static_cast<double>(d[t]), f = 0.0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      const double cr = static_cast<double>(c[t * K + r]);
+      e += cr * y[u + 1][r];
+      f += cr * lam[u + 1][r];
+    }
+#pragma unroll
+    for (int r = 0; r < K; ++r) dc[t * K + r] = static_cast<TIO>(-wg2 * (e * lam[u + 1][r] + f * y[u + 1][r]));
+    dd[t] = static_cast<TIO>(wg2 * f);
+    dwg += -2.0 * p.wg * e * f;
+  }
+  if (a == 0) {
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+      if (r < p.n_init) {
+        du0[r] = static_cast<TIO>(wi2 * lam[1][r]);
+        dwi += -2.0 * p.wi * (y[1][r] - p.u0[r]) * lam[1][r];
+      }
+  }
+#pragma unroll
+  for (int u = -1; u < L; ++u) {
+    const int64_t t = a + u;
+    if (t < 0) continue;
+    if (t + 1 > last) break;
+    double gs = 0.0, gw = 0.0;
+    pair_grad<K>(static_cast<double>(s[t]), p.ws, y[u + 1], y[u + 2 <= L ? u + 2 : L], lam[u + 1],
+                 lam[u + 2 <= L ? u + 2 : L], gs, gw);
+    ds[t] = static_cast<TIO>(gs);
+    dws += gw;
+  }
+  if (!G.has_right) ds[n - 1] = static_cast<TIO>(0.0);
+  dw[0] = dwg;
+  dw[1] = dwi;
+  dw[2] = dws;
+}
+
+// Node data of a reduced (separator) level: records written by the level
+// below.  rec[node] = {A packed (Q), B = block (node+1, node) (K*K)}.
+template <int K>
+struct SrcN {
+  const double* rec;  // [n][Q + KK] of this instance
+  const double* rhs;  // [n][K]
+  SMNN_HD void load(int64_t i, double (&A)[Dim<K>::Q], double (&f)[K]) const {
+    constexpr int R = Dim<K>::Q + Dim<K>::KK;
+#pragma unroll
+    for (int e = 0; e < Dim<K>::Q; ++e) A[e] = rec[i * R + e];
+#pragma unroll
+    for (int e = 0; e < K; ++e) f[e] = rhs[i * K + e];
+  }
+  SMNN_HD void coupling(int64_t i, double (&B)[Dim<K>::KK]) const {
+    constexpr int R = Dim<K>::Q + Dim<K>::KK;
+#pragma unroll
+    for (int e = 0; e < Dim<K>::KK; ++e) B[e] = rec[i * R + Dim<K>::Q + e];
+  }
+};
+
+// Record of a separator node combined from the two chunks that share it:
+// rh = reduction of the chunk on its left (which owns it), lh = reduction of
+// the chunk on its right.
+template <int K>
+SMNN_HD void combine_separator(const double (&rA)[Dim<K>::Q], const double (&rf)[K],
+                               const Reduced<K>& lh, double* rec, double* rhs, bool write_rec) {
+  constexpr int Q = Dim<K>::Q, KK = Dim<K>::KK;
+  if (write_rec) {
+#pragma unroll
+    for (int e = 0; e < Q; ++e) rec[e] = rA[e] + lh.lA[e];
+#pragma unroll
+    for (int e = 0; e < KK; ++e) rec[Q + e] = lh.lB[e];
+  }
+#pragma unroll
+  for (int e = 0; e < K; ++e) rhs[e] = rf[e] + lh.lf[e];
+}
+
+}  // namespace smnn

@@ -1,0 +1,72 @@
+// Interface between the C-ABI host code (smnn_api.cpp) and the kernels
+// (smnn_kernels.hip).  Internal; not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smnn {
+
+// Device view of one level of the partition.
+struct LevelDev {
+  const int32_t* chunk_inst = nullptr;  // [chunks]
+  const int64_t* chunk_off = nullptr;   // [N+1]
+  const int64_t* node_off = nullptr;    // [N+1]
+  int64_t chunks = 0, nodes = 0;
+  double* rec = nullptr;                // level >= 1: [nodes][Q+KK] (in the factor buffer)
+  double* rhs = nullptr;                // level >= 1: [nodes][K]    (workspace)
+  double* x = nullptr;                  // level >= 1: [nodes][K]    (workspace)
+};
+
+// Level-0 (per time step) arrays of one call.  Element type is double or
+// float (fp32 I/O form) for every pointer typed void.
+struct Level0Args {
+  const void* c = nullptr;   // [S][K]
+  const void* d = nullptr;   // [S]
+  const void* s = nullptr;   // [S]
+  const void* u0 = nullptr;  // [N][n_init]
+  const void* w = nullptr;   // [N][3]
+  const void* g = nullptr;   // [S][K]  dl/dy
+  const void* v = nullptr;   // [S][K]  previous iterate (refinement passes)
+  void* out = nullptr;       // [S][K]  result (x, or v + x)
+  const void* y = nullptr;   // [S][K]  forward solution (gradient pass)
+  void* dc = nullptr;        // [S][K]
+  void* dd = nullptr;        // [S]
+  void* ds = nullptr;        // [S]
+  void* du0 = nullptr;       // [N][n_init]
+  double* dw_part = nullptr; // [chunks0][3] per-chunk partial sums
+  void* dw = nullptr;        // [N][3]
+  uint32_t* info = nullptr;  // [N] smallest failing step + 1 (UINT32_MAX = none)
+  int n_init = 0;
+  int64_t N = 0;
+};
+
+struct Launch {
+  int block = 256;      // threads per workgroup (multiple of 64)
+  int max_blocks = 0;   // 0: one wave per tile; >0: persistent grid-stride cap
+};
+
+enum OutMode : int { OUT_STORE = 0, OUT_GRAD = 1 };
+
+// All return hipSuccess or the launch error.  K = R+1, L = chunk length,
+// f32 selects the float I/O form.
+hipError_t launch_reduce0(int K, int L, bool f32, int rhs_mode, bool write_rec, const LevelDev& l0,
+                          const LevelDev& l1, const Level0Args& a, const Launch& cfg, hipStream_t st);
+hipError_t launch_reduceN(int K, int L, bool write_rec, int level, const LevelDev& l, const LevelDev& lnext,
+                          const Level0Args& a, const Launch& cfg, hipStream_t st);
+hipError_t launch_backsubN(int K, int L, int level, const LevelDev& l, const LevelDev* lnext,
+                           const Level0Args& a, const Launch& cfg, hipStream_t st);
+hipError_t launch_backsub0(int K, int L, bool f32, int rhs_mode, int out_mode, const LevelDev& l0,
+                           const LevelDev* l1, const Level0Args& a, const Launch& cfg, hipStream_t st);
+hipError_t launch_dw_reduce(bool f32, const LevelDev& l0, const Level0Args& a, hipStream_t st);
+hipError_t launch_info_init(const Level0Args& a, hipStream_t st);
+hipError_t launch_info_finalize(const Level0Args& a, int32_t* info, hipStream_t st);
+
+bool supported(int K, int L);
+
+// Name of a per-block-size launcher (smnn_kernels.hip is built once per K).
+#define SMNN_KFN_CAT2(a, b) a##_k##b
+#define SMNN_KFN_CAT(a, b) SMNN_KFN_CAT2(a, b)
+#define SMNN_KFN(name) SMNN_KFN_CAT(name, SMNN_TU_K)
+
+}  // namespace smnn

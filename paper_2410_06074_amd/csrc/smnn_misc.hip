@@ -1,0 +1,124 @@
+// Small bookkeeping kernels of the solve (independent of the block size).
+#include <hip/hip_runtime.h>
+
+#include "smnn_internal.h"
+
+namespace smnn {
+namespace {
+
+// Sum the per-chunk weight-gradient partials of each instance: one
+// workgroup per instance, strided per-thread sums then a fixed-shape tree in
+// LDS, so the result does not depend on scheduling.
+template <class TIO>
+__global__ void __launch_bounds__(256) k_dw_reduce(LevelDev l0, Level0Args a) {
+  __shared__ double part[3][256];
+  const int64_t i = blockIdx.x;
+  const int tid = threadIdx.x;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t g = l0.chunk_off[i] + tid; g < l0.chunk_off[i + 1]; g += 256)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) acc[e] += a.dw_part[g * 3 + e];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) part[e][tid] = acc[e];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) part[e][tid] += part[e][tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    TIO* dw = static_cast<TIO*>(a.dw);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) dw[i * 3 + e] = static_cast<TIO>(part[e][0]);
+  }
+}
+
+__global__ void k_info_init(uint32_t* info, int64_t N) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < N) info[i] = 0xFFFFFFFFu;
+}
+
+__global__ void k_info_finalize(const uint32_t* ws, int32_t* info, int64_t N) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < N) info[i] = ws[i] == 0xFFFFFFFFu ? 0 : static_cast<int32_t>(ws[i]);
+}
+
+}  // namespace
+
+hipError_t launch_dw_reduce(bool f32, const LevelDev& l0, const Level0Args& a, hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>(a.N)), block(256);
+  if (f32) hipLaunchKernelGGL(k_dw_reduce<float>, grid, block, 0, st, l0, a);
+  else hipLaunchKernelGGL(k_dw_reduce<double>, grid, block, 0, st, l0, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_info_init(const Level0Args& a, hipStream_t st) {
+  if (!a.info) return hipSuccess;
+  const dim3 grid(static_cast<unsigned>((a.N + 255) / 256)), block(256);
+  hipLaunchKernelGGL(k_info_init, grid, block, 0, st, a.info, a.N);
+  return hipGetLastError();
+}
+
+hipError_t launch_info_finalize(const Level0Args& a, int32_t* info, hipStream_t st) {
+  if (!a.info || !info) return hipSuccess;
+  const dim3 grid(static_cast<unsigned>((a.N + 255) / 256)), block(256);
+  hipLaunchKernelGGL(k_info_finalize, grid, block, 0, st, a.info, info, a.N);
+  return hipGetLastError();
+}
+
+// Dispatch on the block size to the per-K translation units.
+#define SMNN_DECL(KV)                                                                                   \
+  bool supported_k##KV(int, int);                                                                       \
+  hipError_t launch_reduce0_k##KV(int, int, bool, int, bool, const LevelDev&, const LevelDev&,           \
+                                  const Level0Args&, const Launch&, hipStream_t);                        \
+  hipError_t launch_backsub0_k##KV(int, int, bool, int, int, const LevelDev&, const LevelDev*,           \
+                                   const Level0Args&, const Launch&, hipStream_t);                       \
+  hipError_t launch_reduceN_k##KV(int, int, bool, int, const LevelDev&, const LevelDev&, const Level0Args&, \
+                                  const Launch&, hipStream_t);                                           \
+  hipError_t launch_backsubN_k##KV(int, int, int, const LevelDev&, const LevelDev*, const Level0Args&,    \
+                                   const Launch&, hipStream_t);
+SMNN_DECL(2)
+SMNN_DECL(3)
+SMNN_DECL(4)
+SMNN_DECL(5)
+#undef SMNN_DECL
+
+#define SMNN_SWITCH(FN, ...)                     \
+  switch (K) {                                   \
+    case 2: return FN##_k2(__VA_ARGS__);         \
+    case 3: return FN##_k3(__VA_ARGS__);         \
+    case 4: return FN##_k4(__VA_ARGS__);         \
+    case 5: return FN##_k5(__VA_ARGS__);         \
+  }
+
+bool supported(int K, int L) {
+  SMNN_SWITCH(supported, K, L)
+  return false;
+}
+
+hipError_t launch_reduce0(int K, int L, bool f32, int rhs_mode, bool write_rec, const LevelDev& l0,
+                          const LevelDev& l1, const Level0Args& a, const Launch& cfg, hipStream_t st) {
+  SMNN_SWITCH(launch_reduce0, K, L, f32, rhs_mode, write_rec, l0, l1, a, cfg, st)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_backsub0(int K, int L, bool f32, int rhs_mode, int out_mode, const LevelDev& l0,
+                           const LevelDev* l1, const Level0Args& a, const Launch& cfg, hipStream_t st) {
+  SMNN_SWITCH(launch_backsub0, K, L, f32, rhs_mode, out_mode, l0, l1, a, cfg, st)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduceN(int K, int L, bool write_rec, int level, const LevelDev& l, const LevelDev& lnext,
+                          const Level0Args& a, const Launch& cfg, hipStream_t st) {
+  SMNN_SWITCH(launch_reduceN, K, L, write_rec, level, l, lnext, a, cfg, st)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_backsubN(int K, int L, int level, const LevelDev& l, const LevelDev* lnext,
+                           const Level0Args& a, const Launch& cfg, hipStream_t st) {
+  SMNN_SWITCH(launch_backsubN, K, L, level, l, lnext, a, cfg, st)
+  return hipErrorInvalidValue;
+}
+
+}  // namespace smnn

@@ -1,0 +1,283 @@
+// Host build of the per-lane arithmetic in paper_2410_06074_amd/csrc/smnn_core.h,
+// driven through the same level / chunk / separator schedule the HIP kernels
+// use, one chunk after another.  Test tool only: it checks the partition
+// indexing and the recursion on the CPU (under AddressSanitizer) before any
+// kernel runs on a GPU.  The product library never uses it.
+#include <string.h>
+
+#include <algorithm>
+#include <type_traits>
+#include <vector>
+
+#include "../../paper_2410_06074_amd/csrc/smnn_core.h"
+#include "../../paper_2410_06074_amd/csrc/smnn_levels.h"
+
+using namespace smnn;
+
+namespace {
+
+template <int K, int L, class TIO>
+struct Emu {
+  static constexpr int Q = Dim<K>::Q, KK = Dim<K>::KK, REC = Q + KK;
+  int n_init;
+  std::vector<Level> lv;
+  std::vector<std::vector<double>> rec, rhs, x;   // per level >= 1
+  const TIO *c, *d, *s, *u0, *w;
+
+  Inst<K> inst(int64_t i) const {
+    Inst<K> p{};
+    p.wg = (double)w[3 * i]; p.wi = (double)w[3 * i + 1]; p.ws = (double)w[3 * i + 2];
+    p.n_init = n_init;
+    for (int r = 0; r < K; ++r) p.u0[r] = r < n_init ? (double)u0[i * n_init + r] : 0.0;
+    return p;
+  }
+
+  template <int RHS>
+  Src0<K, TIO, RHS> src0(int64_t i, const TIO* g, const TIO* v) const {
+    Src0<K, TIO, RHS> S;
+    const int64_t o = lv[0].node_off[i];
+    S.c = c + o * K; S.d = d + o; S.s = s + o;
+    S.g = g ? g + o * K : nullptr; S.v = v ? v + o * K : nullptr;
+    S.n = lv[0].n[i]; S.p = inst(i);
+    return S;
+  }
+
+  SrcN<K> srcN(int l, int64_t i) const {
+    SrcN<K> S;
+    const int64_t o = lv[l].node_off[i];
+    S.rec = rec[l].data() + o * REC; S.rhs = rhs[l].data() + o * K;
+    return S;
+  }
+
+  // reduce level l (0: from inputs) into level l+1 records / rhs
+  template <int RHS>
+  void reduce(int l, bool write_rec, const TIO* g, const TIO* v) {
+    const Level& lvl = lv[l];
+    const Level& nxt = lv[l + 1];
+    Reduced<K> prev{};
+    for (int64_t ch = 0; ch < lvl.chunks; ++ch) {
+      const int64_t i = lvl.chunk_inst[ch];
+      const int64_t j = ch - lvl.chunk_off[i];
+      const ChunkGeom G = chunk_geom(j, lvl.n[i], L);
+      Reduced<K> cur{};
+      if (G.has_left || G.has_right) {
+        if (l == 0) reduce_chunk<K, L>(src0<RHS>(i, g, v), G.a, G.b, G.has_left, G.has_right, cur);
+        else reduce_chunk<K, L>(srcN(l, i), G.a, G.b, G.has_left, G.has_right, cur);
+      }
+      if (G.has_left) {
+        const int64_t node = nxt.node_off[i] + j - 1;
+        combine_separator<K>(prev.rA, prev.rf, cur, rec[l + 1].data() + node * REC,
+                             rhs[l + 1].data() + node * K, write_rec);
+      }
+      prev = cur;
+    }
+  }
+
+  // back-substitute level l >= 1
+  void backsubN(int l) {
+    const Level& lvl = lv[l];
+    for (int64_t ch = 0; ch < lvl.chunks; ++ch) {
+      const int64_t i = lvl.chunk_inst[ch];
+      const int64_t j = ch - lvl.chunk_off[i];
+      const ChunkGeom G = chunk_geom(j, lvl.n[i], L);
+      double xl[K] = {}, xr[K] = {}, xs[L][K];
+      const int64_t up = (l + 1 < (int)lv.size()) ? lv[l + 1].node_off[i] : 0;
+      if (G.has_left) for (int e = 0; e < K; ++e) xl[e] = x[l + 1][(up + j - 1) * K + e];
+      if (G.has_right) for (int e = 0; e < K; ++e) xr[e] = x[l + 1][(up + j) * K + e];
+      backsub_chunk<K, L>(srcN(l, i), G.a, G.b, G.has_left, G.has_right, xl, xr, xs);
+      const int64_t o = lvl.node_off[i];
+      for (int64_t u = 0; u <= G.b - G.a; ++u)
+        for (int e = 0; e < K; ++e) x[l][(o + G.a + u) * K + e] = xs[u][e];
+      if (G.has_right)
+        for (int e = 0; e < K; ++e) x[l][(o + G.b + 1) * K + e] = xr[e];
+    }
+  }
+
+  // level-0 back-substitution: out = (v ? v : 0) + x  for every owned node
+  template <int RHS>
+  void backsub0(const TIO* g, const TIO* v, TIO* out, std::vector<double>* full) {
+    const Level& lvl = lv[0];
+    for (int64_t ch = 0; ch < lvl.chunks; ++ch) {
+      const int64_t i = lvl.chunk_inst[ch];
+      const int64_t j = ch - lvl.chunk_off[i];
+      const ChunkGeom G = chunk_geom(j, lvl.n[i], L);
+      double xl[K] = {}, xr[K] = {}, xs[L][K];
+      const int64_t up = lv.size() > 1 ? lv[1].node_off[i] : 0;
+      if (G.has_left) for (int e = 0; e < K; ++e) xl[e] = x[1][(up + j - 1) * K + e];
+      if (G.has_right) for (int e = 0; e < K; ++e) xr[e] = x[1][(up + j) * K + e];
+      backsub_chunk<K, L>(src0<RHS>(i, g, v), G.a, G.b, G.has_left, G.has_right, xl, xr, xs);
+      const int64_t o = lvl.node_off[i];
+      const int64_t last = G.has_right ? G.b + 1 : G.b;
+      for (int64_t t = G.a; t <= last; ++t)
+        for (int e = 0; e < K; ++e) {
+          const double xv = (t <= G.b) ? xs[t - G.a][e] : xr[e];
+          const double val = (v ? (double)v[(o + t) * K + e] : 0.0) + xv;
+          if (out) out[(o + t) * K + e] = (TIO)val;
+          if (full) (*full)[(o + t) * K + e] = val;
+        }
+    }
+  }
+
+  // level-0 back-substitution that forms the gradients (mirrors OUT_GRAD)
+  template <int RHS>
+  void backsub0_grad(const TIO* g, const TIO* v, const TIO* y, TIO* dc, TIO* dd, TIO* ds, TIO* du0,
+                     std::vector<double>& dw_part) {
+    constexpr bool ADD = (RHS == RHS_RESID || RHS == RHS_GRESID);
+    const Level& lvl = lv[0];
+    dw_part.assign(lvl.chunks * 3, 0.0);
+    for (int64_t ch = 0; ch < lvl.chunks; ++ch) {
+      const int64_t i = lvl.chunk_inst[ch];
+      const int64_t j = ch - lvl.chunk_off[i];
+      const ChunkGeom G = chunk_geom(j, lvl.n[i], L);
+      double xl[K] = {}, xr[K] = {}, xs[L][K];
+      const int64_t up = lv.size() > 1 ? lv[1].node_off[i] : 0;
+      if (G.has_left) for (int e = 0; e < K; ++e) xl[e] = x[1][(up + j - 1) * K + e];
+      if (G.has_right) for (int e = 0; e < K; ++e) xr[e] = x[1][(up + j) * K + e];
+      const auto S = src0<RHS>(i, g, v);
+      backsub_chunk<K, L>(S, G.a, G.b, G.has_left, G.has_right, xl, xr, xs);
+      const int64_t o = lvl.node_off[i];
+      const int64_t last = G.has_right ? G.b + 1 : G.b;
+      double lam[L + 1][K], yv[L + 1][K];
+      for (int u = -1; u < L; ++u) {
+        const int64_t t = G.a + u;
+        const bool in = t >= 0 && t <= last;
+        for (int e = 0; e < K; ++e) {
+          double xv = 0.0;
+          if (u == -1) xv = xl[e];
+          else if (t <= G.b) xv = xs[u][e];
+          else xv = xr[e];
+          if (ADD && in) xv += (double)v[(o + t) * K + e];
+          lam[u + 1][e] = in ? xv : 0.0;
+          yv[u + 1][e] = in ? (double)y[(o + t) * K + e] : 0.0;
+        }
+      }
+      double dwp[3];
+      grad_chunk<K, L, TIO>(S.c, S.d, S.s, S.n, S.p, G, lam, yv, dc + o * K, dd + o, ds + o, du0 + i * n_init, dwp);
+      for (int e = 0; e < 3; ++e) dw_part[ch * 3 + e] = dwp[e];
+    }
+  }
+
+  template <int RHS>
+  void solve(bool write_rec, const TIO* g, const TIO* v, TIO* out, std::vector<double>* full) {
+    const int nl = (int)lv.size();
+    for (int l = 0; l + 1 < nl; ++l) {
+      if (l == 0) reduce<RHS>(0, write_rec, g, v);
+      else reduce<RHS_BETA>(l, write_rec, nullptr, nullptr);
+    }
+    for (int l = nl - 1; l >= 1; --l) backsubN(l);
+    backsub0<RHS>(g, v, out, full);
+  }
+
+  void alloc() {
+    rec.assign(lv.size(), {}); rhs.assign(lv.size(), {}); x.assign(lv.size(), {});
+    for (size_t l = 1; l < lv.size(); ++l) {
+      rec[l].assign(lv[l].nodes * REC, 0.0);
+      rhs[l].assign(lv[l].nodes * K, 0.0);
+      x[l].assign(lv[l].nodes * K, 0.0);
+    }
+  }
+};
+
+// level >= 1 reductions read records, not inputs: specialise reduce() for that
+template <int K, int L, class TIO>
+struct Runner {
+  static int forward(int n_init, int64_t N, const int64_t* T, const TIO* c, const TIO* d, const TIO* s,
+                     const TIO* u0, const TIO* w, TIO* y, int refine) {
+    Emu<K, L, TIO> E;
+    E.n_init = n_init;
+    E.lv = build_levels(std::vector<int64_t>(T, T + N), L);
+    E.c = c; E.d = d; E.s = s; E.u0 = u0; E.w = w;
+    E.alloc();
+    const int64_t S = E.lv[0].nodes;
+    std::vector<TIO> b0(S * K), b1(S * K);
+    TIO* bufs[2] = {b0.data(), b1.data()};
+    TIO* dst = refine == 0 ? y : bufs[0];
+    E.template solve<RHS_BETA>(true, nullptr, nullptr, dst, nullptr);
+    for (int m = 1; m <= refine; ++m) {
+      TIO* prev = dst;
+      dst = (m == refine) ? y : bufs[m % 2];
+      E.template solve<RHS_RESID>(false, nullptr, prev, dst, nullptr);
+    }
+    return 0;
+  }
+
+  static int backward(int n_init, int64_t N, const int64_t* T, const TIO* c, const TIO* d, const TIO* s,
+                      const TIO* u0, const TIO* w, const TIO* y, const TIO* gy, TIO* dc, TIO* dd, TIO* ds,
+                      TIO* du0, TIO* dw, int refine) {
+    Emu<K, L, TIO> E;
+    E.n_init = n_init;
+    E.lv = build_levels(std::vector<int64_t>(T, T + N), L);
+    E.c = c; E.d = d; E.s = s; E.u0 = u0; E.w = w;
+    E.alloc();
+    const int64_t S = E.lv[0].nodes;
+    std::vector<TIO> b0(S * K), b1(S * K);
+    TIO* bufs[2] = {b0.data(), b1.data()};
+    std::vector<double> dwp;
+    const int nl = (int)E.lv.size();
+    auto upper = [&](auto rhs_tag, const TIO* v) {
+      constexpr int RHS = decltype(rhs_tag)::value;
+      for (int l = 0; l + 1 < nl; ++l) {
+        if (l == 0) E.template reduce<RHS>(0, false, gy, v);
+        else E.template reduce<RHS_BETA>(l, false, nullptr, nullptr);
+      }
+      for (int l = nl - 1; l >= 1; --l) E.backsubN(l);
+    };
+    // the factor records come from a forward pass on the same inputs
+    E.template solve<RHS_BETA>(true, nullptr, nullptr, b1.data(), nullptr);
+    if (refine == 0) {
+      upper(std::integral_constant<int, RHS_G>{}, nullptr);
+      E.template backsub0_grad<RHS_G>(gy, nullptr, y, dc, dd, ds, du0, dwp);
+    } else {
+      TIO* dst = bufs[0];
+      E.template solve<RHS_G>(false, gy, nullptr, dst, nullptr);
+      for (int m = 1; m <= refine; ++m) {
+        TIO* prev = dst;
+        if (m == refine) {
+          upper(std::integral_constant<int, RHS_GRESID>{}, prev);
+          E.template backsub0_grad<RHS_GRESID>(gy, prev, y, dc, dd, ds, du0, dwp);
+        } else {
+          dst = bufs[m % 2];
+          E.template solve<RHS_GRESID>(false, gy, prev, dst, nullptr);
+        }
+      }
+    }
+    for (int64_t i = 0; i < N; ++i) {
+      double acc[3] = {0, 0, 0};
+      for (int64_t ch = E.lv[0].chunk_off[i]; ch < E.lv[0].chunk_off[i + 1]; ++ch)
+        for (int e = 0; e < 3; ++e) acc[e] += dwp[ch * 3 + e];
+      for (int e = 0; e < 3; ++e) dw[i * 3 + e] = (TIO)acc[e];
+    }
+    return 0;
+  }
+};
+
+}  // namespace
+
+#define DISPATCH(KV, LV, FN, ...)                                                      \
+  if (K == KV && Lc == LV) return Runner<KV, LV, TYPE>::FN(__VA_ARGS__);
+
+extern "C" {
+#define TYPE double
+int emu_forward_f64(int K, int Lc, int n_init, int64_t N, const int64_t* T, const double* c, const double* d,
+                    const double* s, const double* u0, const double* w, double* y, int refine) {
+  DISPATCH(2, 4, forward, n_init, N, T, c, d, s, u0, w, y, refine)
+  DISPATCH(3, 4, forward, n_init, N, T, c, d, s, u0, w, y, refine)
+  DISPATCH(3, 8, forward, n_init, N, T, c, d, s, u0, w, y, refine)
+  DISPATCH(4, 4, forward, n_init, N, T, c, d, s, u0, w, y, refine)
+  DISPATCH(4, 8, forward, n_init, N, T, c, d, s, u0, w, y, refine)
+  DISPATCH(5, 4, forward, n_init, N, T, c, d, s, u0, w, y, refine)
+  return -1;
+}
+int emu_backward_f64(int K, int Lc, int n_init, int64_t N, const int64_t* T, const double* c, const double* d,
+                     const double* s, const double* u0, const double* w, const double* y, const double* gy,
+                     double* dc, double* dd, double* ds, double* du0, double* dw, int refine) {
+  DISPATCH(2, 4, backward, n_init, N, T, c, d, s, u0, w, y, gy, dc, dd, ds, du0, dw, refine)
+  DISPATCH(3, 4, backward, n_init, N, T, c, d, s, u0, w, y, gy, dc, dd, ds, du0, dw, refine)
+  DISPATCH(3, 8, backward, n_init, N, T, c, d, s, u0, w, y, gy, dc, dd, ds, du0, dw, refine)
+  DISPATCH(4, 4, backward, n_init, N, T, c, d, s, u0, w, y, gy, dc, dd, ds, du0, dw, refine)
+  DISPATCH(4, 8, backward, n_init, N, T, c, d, s, u0, w, y, gy, dc, dd, ds, du0, dw, refine)
+  DISPATCH(5, 4, backward, n_init, N, T, c, d, s, u0, w, y, gy, dc, dd, ds, du0, dw, refine)
+  return -1;
+}
+#undef TYPE
+}

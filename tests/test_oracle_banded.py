@@ -110,3 +110,14 @@ def test_banded_backward_error_long_sequence():
                 absg[t] += np.abs(a[:k]) * (np.abs(a) @ np.abs(yy)); absg[t + 1] += np.abs(a[k:]) * (np.abs(a) @ np.abs(yy))
     eta = float(np.abs(g).max() / np.abs(absg).max())
     assert eta < 1e-14
+
+
+def test_condition_estimate_matches_dense_svd():
+    from oracle import dense as D
+    bt = gaussian_batch(2, [6, 60], R=2, seed=4)
+    kap = banded.cond(bt)
+    for i in range(bt.n_inst):
+        c, d, s, u0, w = bt.instance(i)
+        M, _ = D.normal_matrix(c, d, s, u0, w)
+        ref = np.linalg.cond(M)
+        assert abs(kap[i] - ref) <= 0.05 * ref
