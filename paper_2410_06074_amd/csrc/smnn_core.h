@@ -269,9 +269,19 @@ SMNN_HD void coupling_block(const double (&pw)[Dim<K>::P], double ws2, double (&
 // Row residuals of the 2K weighted smoothness rows of a pair (Eqs. 6-7 scaled
 // by w_s s^r) at (v_t, v_{t+1}): rho = -(a . v); returns the contributions
 // a^T rho to the left node (cl) and to the right node (cr).
+//
+// The residual of an iterate near the solution is a small difference of
+// large terms, so its rounding noise is a sizeable part of its value.  That
+// noise is harmless only if every kernel that evaluates the residual of a
+// node (the reduce and the back-substitution passes) rounds it identically,
+// so contraction into FMAs -- which the compiler may decide differently in
+// different kernels -- is switched off here and in residual_rhs below.
 template <int K>
 SMNN_HD void pair_residual(const double (&pw)[Dim<K>::P], double ws, const double (&vt)[K],
                            const double (&vn)[K], double (&cl)[K], double (&cr)[K]) {
+#if defined(__clang__)
+#pragma clang fp contract(off)
+#endif
   constexpr Coef<K> C{};
 #pragma unroll
   for (int j = 0; j < K; ++j) { cl[j] = 0.0; cr[j] = 0.0; }
@@ -551,6 +561,45 @@ struct Src0 {
     coupling_block<K>(pw, p.ws * p.ws, B);
   }
 
+  // f = A^T W (b - A v) (RHS_RESID) or g - A^T W A v (RHS_GRESID) at node i,
+  // evaluated row by row from the constraint rows touching the node.
+  SMNN_HD void residual_rhs(int64_t i, const double (&ci)[K], bool has_next, bool has_prev,
+                            const double (&pl)[Dim<K>::P], const double (&pr)[Dim<K>::P], double (&f)[K]) const {
+#if defined(__clang__)
+#pragma clang fp contract(off)
+#endif
+    const double wg2 = p.wg * p.wg, wi2 = p.wi * p.wi;
+    double vi[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) vi[r] = ld(v, i * K + r);
+    double e = (RHS == RHS_RESID) ? ld(d, i) : 0.0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) e -= ci[r] * vi[r];
+#pragma unroll
+    for (int r = 0; r < K; ++r) f[r] = (RHS == RHS_GRESID ? ld(g, i * K + r) : 0.0) + wg2 * ci[r] * e;
+    if (i == 0) {
+#pragma unroll
+      for (int r = 0; r < K; ++r)
+        if (r < p.n_init) f[r] += wi2 * ((RHS == RHS_RESID ? p.u0[r] : 0.0) - vi[r]);
+    }
+    if (has_next) {
+      double vn[K], cl[K], cr[K];
+#pragma unroll
+      for (int r = 0; r < K; ++r) vn[r] = ld(v, (i + 1) * K + r);
+      pair_residual<K>(pr, p.ws, vi, vn, cl, cr);
+#pragma unroll
+      for (int r = 0; r < K; ++r) f[r] += cl[r];
+    }
+    if (has_prev) {
+      double vp[K], cl[K], cr[K];
+#pragma unroll
+      for (int r = 0; r < K; ++r) vp[r] = ld(v, (i - 1) * K + r);
+      pair_residual<K>(pl, p.ws, vp, vi, cl, cr);
+#pragma unroll
+      for (int r = 0; r < K; ++r) f[r] += cr[r];
+    }
+  }
+
   SMNN_HD void load(int64_t i, double (&A)[Dim<K>::Q], double (&f)[K]) const {
     double ci[K];
 #pragma unroll
@@ -588,36 +637,7 @@ struct Src0 {
 #pragma unroll
       for (int r = 0; r < K; ++r) f[r] = ld(g, i * K + r);
     } else {
-      // residual A^T W (b - A v) row by row; b = 0 for the adjoint (RHS_GRESID)
-      double vi[K];
-#pragma unroll
-      for (int r = 0; r < K; ++r) vi[r] = ld(v, i * K + r);
-      double e = (RHS == RHS_RESID) ? ld(d, i) : 0.0;
-#pragma unroll
-      for (int r = 0; r < K; ++r) e -= ci[r] * vi[r];
-#pragma unroll
-      for (int r = 0; r < K; ++r) f[r] = (RHS == RHS_GRESID ? ld(g, i * K + r) : 0.0) + wg2 * ci[r] * e;
-      if (i == 0) {
-#pragma unroll
-        for (int r = 0; r < K; ++r)
-          if (r < p.n_init) f[r] += wi2 * ((RHS == RHS_RESID ? p.u0[r] : 0.0) - vi[r]);
-      }
-      if (has_next) {
-        double vn[K], cl[K], cr[K];
-#pragma unroll
-        for (int r = 0; r < K; ++r) vn[r] = ld(v, (i + 1) * K + r);
-        pair_residual<K>(pr, p.ws, vi, vn, cl, cr);
-#pragma unroll
-        for (int r = 0; r < K; ++r) f[r] += cl[r];
-      }
-      if (has_prev) {
-        double vp[K], cl[K], cr[K];
-#pragma unroll
-        for (int r = 0; r < K; ++r) vp[r] = ld(v, (i - 1) * K + r);
-        pair_residual<K>(pl, p.ws, vp, vi, cl, cr);
-#pragma unroll
-        for (int r = 0; r < K; ++r) f[r] += cr[r];
-      }
+      residual_rhs(i, ci, has_next, has_prev, pl, pr, f);
     }
   }
 };

@@ -201,6 +201,26 @@ struct Runner {
     return 0;
   }
 
+  // one refinement pass from a given iterate v: out = v + M^{-1} A^T W (b - A v)
+  static int refine_from(int n_init, int64_t N, const int64_t* T, const TIO* c, const TIO* d, const TIO* s,
+                         const TIO* u0, const TIO* w, const TIO* v, TIO* out) {
+    Emu<K, L, TIO> E;
+    E.n_init = n_init;
+    E.lv = build_levels(std::vector<int64_t>(T, T + N), L);
+    E.c = c; E.d = d; E.s = s; E.u0 = u0; E.w = w;
+    E.alloc();
+    std::vector<TIO> tmp(E.lv[0].nodes * K);
+    E.template solve<RHS_BETA>(true, nullptr, nullptr, tmp.data(), nullptr);
+    E.template solve<RHS_RESID>(false, nullptr, v, out, nullptr);
+    if (dbg_rhs1 && E.lv.size() > 1) {
+      std::copy(E.rhs[1].begin(), E.rhs[1].end(), dbg_rhs1);
+      std::copy(E.x[1].begin(), E.x[1].end(), dbg_x1);
+    }
+    return 0;
+  }
+  static inline double* dbg_rhs1 = nullptr;
+  static inline double* dbg_x1 = nullptr;
+
   static int backward(int n_init, int64_t N, const int64_t* T, const TIO* c, const TIO* d, const TIO* s,
                       const TIO* u0, const TIO* w, const TIO* y, const TIO* gy, TIO* dc, TIO* dd, TIO* ds,
                       TIO* du0, TIO* dw, int refine) {
@@ -267,6 +287,27 @@ int emu_forward_f64(int K, int Lc, int n_init, int64_t N, const int64_t* T, cons
   DISPATCH(4, 8, forward, n_init, N, T, c, d, s, u0, w, y, refine)
   DISPATCH(5, 4, forward, n_init, N, T, c, d, s, u0, w, y, refine)
   return -1;
+}
+int emu_refine_f64(int K, int Lc, int n_init, int64_t N, const int64_t* T, const double* c, const double* d,
+                   const double* s, const double* u0, const double* w, const double* v, double* out) {
+  DISPATCH(2, 4, refine_from, n_init, N, T, c, d, s, u0, w, v, out)
+  DISPATCH(3, 4, refine_from, n_init, N, T, c, d, s, u0, w, v, out)
+  DISPATCH(3, 8, refine_from, n_init, N, T, c, d, s, u0, w, v, out)
+  DISPATCH(4, 4, refine_from, n_init, N, T, c, d, s, u0, w, v, out)
+  DISPATCH(4, 8, refine_from, n_init, N, T, c, d, s, u0, w, v, out)
+  DISPATCH(5, 4, refine_from, n_init, N, T, c, d, s, u0, w, v, out)
+  return -1;
+}
+int emu_refine_debug_f64(int K, int Lc, int n_init, int64_t N, const int64_t* T, const double* c,
+                         const double* d, const double* s, const double* u0, const double* w, const double* v,
+                         double* out, double* rhs1, double* x1) {
+  if (K != 3 || Lc != 8) return -1;
+  Runner<3, 8, double>::dbg_rhs1 = rhs1;
+  Runner<3, 8, double>::dbg_x1 = x1;
+  const int rc = Runner<3, 8, double>::refine_from(n_init, N, T, c, d, s, u0, w, v, out);
+  Runner<3, 8, double>::dbg_rhs1 = nullptr;
+  Runner<3, 8, double>::dbg_x1 = nullptr;
+  return rc;
 }
 int emu_backward_f64(int K, int Lc, int n_init, int64_t N, const int64_t* T, const double* c, const double* d,
                      const double* s, const double* u0, const double* w, const double* y, const double* gy,
