@@ -37,6 +37,9 @@ namespace smnn {
 namespace {
 
 constexpr int WAVE = 64;
+#ifndef SMNN_MIN_WAVES
+#define SMNN_MIN_WAVES 1
+#endif
 
 __device__ __forceinline__ int64_t wave_id() {
   return (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / WAVE;
@@ -97,7 +100,7 @@ __device__ __forceinline__ void exchange_and_write(const Reduced<K>& red, bool w
 
 // ------------------------------------------------------------ level 0 reduce
 template <int K, int L, class TIO, int RHS, bool WREC>
-__global__ void __launch_bounds__(256) k_reduce0(LevelDev l0, LevelDev l1, Level0Args a) {
+__global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduce0(LevelDev l0, LevelDev l1, Level0Args a) {
   constexpr int REC = Dim<K>::Q + Dim<K>::KK;
   const int lane = lane_id();
   const int64_t G = l0.chunks;
@@ -132,7 +135,7 @@ __global__ void __launch_bounds__(256) k_reduce0(LevelDev l0, LevelDev l1, Level
 
 // -------------------------------------------------------- level >= 1 reduce
 template <int K, int L, bool WREC>
-__global__ void __launch_bounds__(256) k_reduceN(LevelDev lv, LevelDev nx, Level0Args a, int level) {
+__global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduceN(LevelDev lv, LevelDev nx, Level0Args a, int level) {
   constexpr int REC = Dim<K>::Q + Dim<K>::KK;
   const int lane = lane_id();
   const int64_t G = lv.chunks;
@@ -169,7 +172,7 @@ __global__ void __launch_bounds__(256) k_reduceN(LevelDev lv, LevelDev nx, Level
 
 // --------------------------------------------------- level >= 1 back-subst.
 template <int K, int L>
-__global__ void __launch_bounds__(256) k_backsubN(LevelDev lv, LevelDev nx, bool has_next, Level0Args a,
+__global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsubN(LevelDev lv, LevelDev nx, bool has_next, Level0Args a,
                                                  int level) {
   constexpr int REC = Dim<K>::Q + Dim<K>::KK;
   const int lane = lane_id();
@@ -212,7 +215,7 @@ __global__ void __launch_bounds__(256) k_backsubN(LevelDev lv, LevelDev nx, bool
 
 // ------------------------------------------------------- level 0 back-subst.
 template <int K, int L, class TIO, int RHS, int OUT>
-__global__ void __launch_bounds__(256) k_backsub0(LevelDev l0, LevelDev l1, bool has_next, Level0Args a) {
+__global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub0(LevelDev l0, LevelDev l1, bool has_next, Level0Args a) {
   constexpr bool ADD = (RHS == RHS_RESID || RHS == RHS_GRESID);
   const int lane = lane_id();
   const int64_t G = l0.chunks;
@@ -356,7 +359,8 @@ hipError_t backsubN_t(int level, const LevelDev& l, const LevelDev* nx, const Le
 }  // namespace
 
 // (K, L) pairs compiled in: L is the chunk length of every level.
-#if SMNN_TU_K == 2
+#ifdef SMNN_FOR_EACH_KL
+#elif SMNN_TU_K == 2
 #define SMNN_FOR_EACH_KL(X) X(2, 8) X(2, 16)
 #elif SMNN_TU_K == 3
 #define SMNN_FOR_EACH_KL(X) X(3, 4) X(3, 8) X(3, 16)
