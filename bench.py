@@ -88,7 +88,7 @@ def describe(name, bt, mode):
 
 
 # --------------------------------------------------------------- GPU run
-def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0):
+def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0):
     import numpy as np
     import torch
     from paper_2410_06074_amd import Plan
@@ -99,7 +99,7 @@ def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0):
     dt = torch.float32 if mode == "fp32r" else torch.float64
     io = 4 if mode == "fp32r" else 8
     steps_arg = int(bt.T[0]) if (bt.T == bt.T[0]).all() else bt.T
-    plan = Plan(bt.R, bt.n_init, bt.n_inst, steps_arg, mode=mode, chunk=chunk)
+    plan = Plan(bt.R, bt.n_init, bt.n_inst, steps_arg, mode=mode, chunk=chunk, chunk_upper=chunk_upper)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt)
     c, b, h, u0, w = t(bt.c), t(bt.b), t(bt.h), t(bt.u0), t(bt.w)
     S, K = plan.total_steps, plan.k
@@ -159,7 +159,7 @@ def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0):
     for j, i in enumerate(sample_idx):
         err = max(err, max(metrics.rel_by_order(yn[o[i]:o[i + 1]], ref[so[j]:so[j + 1]], K)))
     return {"plan": plan, "ms": ms, "ms_traced": ms_traced, "per_kind": per_kind, "step_bytes": step_bytes,
-            "err": err, "levels": plan.levels, "chunk": plan.chunk, "refine": plan.refine_steps}
+            "err": err, "levels": plan.levels, "chunk": [plan.chunk, plan.chunk_upper], "refine": plan.refine_steps}
 
 
 def roofline(res):
@@ -205,7 +205,8 @@ def main():
     ap.add_argument("--side-modes", default="fp64,fp32r", help="extra modes measured (comma list, '' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--chunk", type=int, default=0, help="nodes per lane per level (0: library default)")
+    ap.add_argument("--chunk", type=int, default=0, help="time steps per lane at level 0 (0: library default)")
+    ap.add_argument("--chunk-upper", type=int, default=0, help="nodes per lane at levels >= 1 (0: default)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solve is per-instance independent and this build has no "
@@ -225,7 +226,8 @@ def main():
     results = {}
     for m in modes:
         log("mode", m)
-        results[m] = run_mode(bt, m, args.steps, args.warmup, sample, chunk=args.chunk)
+        results[m] = run_mode(bt, m, args.steps, args.warmup, sample, chunk=args.chunk,
+                              chunk_upper=args.chunk_upper)
         r = results[m]
         log("  %.3f ms/step (traced %.3f), %.3e steps/s, err %.2e, levels %s"
             % (r["ms"], r["ms_traced"], bt.total_steps / (r["ms"] * 1e-3), r["err"], r["levels"]))

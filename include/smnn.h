@@ -101,7 +101,8 @@ typedef struct {
   int64_t steps_uniform;
   int32_t mode;           /* smnn_mode */
   int32_t refine_steps;   /* refinement steps in the refined modes, 0..2; -1: default (1) */
-  int32_t chunk;          /* nodes per lane per level (4, 8 or 16); 0: default for the order */
+  int32_t chunk;          /* nodes per lane at level 0 (time steps; 4, 8 or 16); 0: default for the order */
+  int32_t chunk_upper;    /* nodes per lane at the separator levels >= 1; 0: default for the order */
   int32_t block;          /* threads per workgroup (64..256, multiple of 64); 0: 256 */
   int32_t max_blocks;     /* >0: persistent grid-stride launch with at most this many
                              workgroups per kernel; 0: one wavefront per tile */
@@ -120,12 +121,13 @@ smnn_status smnn_plan_destroy(smnn_plan* plan);
 smnn_status smnn_plan_sizes(const smnn_plan* plan, size_t* factor_bytes, size_t* workspace_bytes,
                             int64_t* total_steps);
 
-/* Introspection: SMNN_Q_LEVELS, SMNN_Q_CHUNK, SMNN_Q_NODES(l), SMNN_Q_CHUNKS(l),
- * SMNN_Q_REFINE, SMNN_Q_MODE.  Returns -1 for an unknown key. */
+/* Introspection: SMNN_Q_LEVELS, SMNN_Q_CHUNK, SMNN_Q_CHUNK_UPPER, SMNN_Q_NODES(l),
+ * SMNN_Q_CHUNKS(l), SMNN_Q_REFINE, SMNN_Q_MODE.  Returns -1 for an unknown key. */
 #define SMNN_Q_LEVELS 1
 #define SMNN_Q_CHUNK 2
 #define SMNN_Q_REFINE 3
 #define SMNN_Q_MODE 4
+#define SMNN_Q_CHUNK_UPPER 5
 #define SMNN_Q_NODES(l) (1000 + (l))
 #define SMNN_Q_CHUNKS(l) (2000 + (l))
 int64_t smnn_plan_query(const smnn_plan* plan, int32_t key);

@@ -14,7 +14,7 @@
 using namespace smnn;
 
 struct smnn_plan {
-  int R = 0, K = 0, n_init = 0, mode = 0, refine = 0, L = 8;
+  int R = 0, K = 0, n_init = 0, mode = 0, refine = 0, L0 = 8, L1 = 8;
   int64_t N = 0, S = 0;
   int device = 0;
   bool f32 = false;
@@ -35,11 +35,12 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-int default_chunk(int K) {
+// Default chunk lengths (level 0, levels >= 1) per block size K.
+int default_chunk(int K, bool upper) {
   switch (K) {
     case 2: return 16;
     case 3: return 8;
-    case 4: return 4;
+    case 4: return upper ? 8 : 4;
     default: return 4;
   }
 }
@@ -105,15 +106,15 @@ smnn_status solve(const smnn_plan* p, const Bound& b, int rhs, bool write_rec, i
   const Tracer tr{p, st};
   if (nl > 1)
     SMNN_LAUNCH(tr, SMNN_K_REDUCE0, 0, rhs, 0,
-                launch_reduce0(p->K, p->L, p->f32, rhs, write_rec, b.lev[0], b.lev[1], a, p->cfg, st));
+                launch_reduce0(p->K, p->L0, p->f32, rhs, write_rec, b.lev[0], b.lev[1], a, p->cfg, st));
   for (int l = 1; l + 1 < nl; ++l)
     SMNN_LAUNCH(tr, SMNN_K_REDUCEN, l, rhs, 0,
-                launch_reduceN(p->K, p->L, write_rec, l, b.lev[l], b.lev[l + 1], a, p->cfg, st));
+                launch_reduceN(p->K, p->L1, write_rec, l, b.lev[l], b.lev[l + 1], a, p->cfg, st));
   for (int l = nl - 1; l >= 1; --l)
     SMNN_LAUNCH(tr, SMNN_K_BACKSUBN, l, rhs, 0,
-                launch_backsubN(p->K, p->L, l, b.lev[l], l + 1 < nl ? &b.lev[l + 1] : nullptr, a, p->cfg, st));
+                launch_backsubN(p->K, p->L1, l, b.lev[l], l + 1 < nl ? &b.lev[l + 1] : nullptr, a, p->cfg, st));
   SMNN_LAUNCH(tr, SMNN_K_BACKSUB0, 0, rhs, out_mode,
-              launch_backsub0(p->K, p->L, p->f32, rhs, out_mode, b.lev[0], nl > 1 ? &b.lev[1] : nullptr, a,
+              launch_backsub0(p->K, p->L0, p->f32, rhs, out_mode, b.lev[0], nl > 1 ? &b.lev[1] : nullptr, a,
                               p->cfg, st));
   return SMNN_OK;
 }
@@ -140,8 +141,10 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   if (d->block < 0 || d->block > 256 || d->block % 64 != 0) return SMNN_ERR_INVALID_ARG;
   if (d->max_blocks < 0) return SMNN_ERR_INVALID_ARG;
   const int K = d->order + 1;
-  const int L = d->chunk ? d->chunk : default_chunk(K);
-  if (!supported(K, L)) return SMNN_ERR_UNSUPPORTED;
+  const int L0 = d->chunk ? d->chunk : default_chunk(K, false);
+  const int L1 = d->chunk_upper ? d->chunk_upper : default_chunk(K, true);
+  if (d->chunk < 0 || d->chunk_upper < 0) return SMNN_ERR_INVALID_ARG;
+  if (!supported(K, L0) || !supported(K, L1)) return SMNN_ERR_UNSUPPORTED;
   std::vector<int64_t> T(static_cast<size_t>(d->n_inst));
   for (int64_t i = 0; i < d->n_inst; ++i) {
     T[i] = d->steps ? d->steps[i] : d->steps_uniform;
@@ -155,14 +158,15 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   p->n_init = d->n_init;
   p->mode = d->mode;
   p->refine = d->mode == SMNN_MODE_FP64 ? 0 : (d->refine_steps < 0 ? 1 : d->refine_steps);
-  p->L = L;
+  p->L0 = L0;
+  p->L1 = L1;
   p->N = d->n_inst;
   p->f32 = d->mode == SMNN_MODE_FP32_REFINED;
   p->cfg.block = d->block ? d->block : 256;
   p->cfg.max_blocks = d->max_blocks;
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return SMNN_ERR_HIP; }
 
-  std::vector<Level> lv = build_levels(T, L);
+  std::vector<Level> lv = build_levels(T, L0, L1);
   p->S = lv[0].nodes;
   const int Q = K * (K + 1) / 2, REC = Q + K * K;
   const size_t io = p->f32 ? sizeof(float) : sizeof(double);
@@ -280,7 +284,8 @@ smnn_status smnn_plan_sizes(const smnn_plan* p, size_t* factor_bytes, size_t* wo
 int64_t smnn_plan_query(const smnn_plan* p, int32_t key) {
   if (!p) return -1;
   if (key == SMNN_Q_LEVELS) return static_cast<int64_t>(p->lev.size());
-  if (key == SMNN_Q_CHUNK) return p->L;
+  if (key == SMNN_Q_CHUNK) return p->L0;
+  if (key == SMNN_Q_CHUNK_UPPER) return p->L1;
   if (key == SMNN_Q_REFINE) return p->refine;
   if (key == SMNN_Q_MODE) return p->mode;
   if (key >= 1000 && key < 1000 + static_cast<int32_t>(p->lev.size())) return p->lev[key - 1000].nodes;
@@ -303,6 +308,8 @@ smnn_status smnn_forward(const smnn_plan* p, const void* c, const void* b, const
   Level0Args a;
   a.c = c; a.d = b; a.s = h; a.u0 = u0; a.w = w;
   a.n_init = p->n_init;
+  a.L0 = p->L0;
+  a.L1 = p->L1;
   a.N = p->N;
   a.info = info ? bd.info : nullptr;
   SMNN_HIP(launch_info_init(a, st));
@@ -337,6 +344,8 @@ smnn_status smnn_backward(const smnn_plan* p, const void* c, const void* b, cons
   a.c = c; a.d = b; a.s = h; a.u0 = u0; a.w = w; a.g = gy; a.y = y;
   a.dc = dc; a.dd = db; a.ds = dh; a.du0 = du0; a.dw = dw; a.dw_part = bd.dwp;
   a.n_init = p->n_init;
+  a.L0 = p->L0;
+  a.L1 = p->L1;
   a.N = p->N;
   a.info = info ? bd.info : nullptr;
   SMNN_HIP(launch_info_init(a, st));

@@ -40,6 +40,14 @@ struct Dim {
 
 SMNN_HD constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
+// Keeps the compiler from hoisting a node's loads above the previous node's
+// arithmetic (which would hold a whole chunk of inputs in registers).
+#if defined(__HIP_DEVICE_COMPILE__) && defined(SMNN_NODE_FENCE)
+#define SMNN_FENCE() asm volatile("" ::: "memory")
+#else
+#define SMNN_FENCE() do {} while (0)
+#endif
+
 // Compile-time coefficients of the smoothness blocks.  With S+ = diag(s^r),
 // F_{ij} = 1/(j-i)! (j >= i) as in App. A.2, every entry of the three blocks
 // a pair of neighbouring nodes contributes is w_s^2 s^{i+j} times a constant:
@@ -74,6 +82,25 @@ struct Coef {
 };
 
 // ---------------------------------------------------------------- algebra
+// 1/sqrt(d).  On the GPU: the hardware reciprocal square root estimate
+// refined by two Newton steps y <- y (3 - d y^2) / 2 (each roughly doubles the
+// number of correct bits), a short dependency chain instead of a correctly
+// rounded square root followed by a correctly rounded division.  Non-positive
+// d gives NaN or Inf, as 1/sqrt does.
+SMNN_HD double rsqrt_pivot(double d) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double y = __builtin_amdgcn_rsq(d);
+  double t = d * y;
+  double e = fma(-t, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  t = d * y;
+  e = fma(-t, y, 1.0);
+  return fma(0.5 * y, e, y);
+#else
+  return 1.0 / sqrt(d);
+#endif
+}
+
 // In-place Cholesky of the packed symmetric matrix D.  On return the strict
 // lower part holds L and the diagonal holds 1/L_jj.  Returns false when a
 // pivot is not > 0 (or is NaN); the NaN then propagates to the results.
@@ -86,7 +113,7 @@ SMNN_HD bool chol(double (&D)[Dim<K>::Q]) {
 #pragma unroll
     for (int m = 0; m < j; ++m) d -= D[tri(j, m)] * D[tri(j, m)];
     ok = ok && (d > 0.0);
-    const double inv = 1.0 / sqrt(d);
+    const double inv = rsqrt_pivot(d);
     D[tri(j, j)] = inv;
 #pragma unroll
     for (int i = j + 1; i < K; ++i) {
@@ -383,8 +410,9 @@ SMNN_HD ChunkGeom chunk_geom(int64_t j, int64_t n, int L) {
 // ------------------------------------------------------------ chunk cores
 // A chunk covers nodes a..b of one instance's block-tridiagonal system.  The
 // node at a-1 (if has_left) and b+1 (if has_right) are separators.  Src
-// supplies   load(i, A, f)   diagonal block and right-hand side of node i,
-//            coupling(i, B)  block (i+1, i).
+// supplies   load(i, A, f, Bp)  diagonal block, right-hand side and (for
+//                               i > 0) block (i, i-1) of node i,
+//            coupling(i, B)     block (i+1, i).
 
 // Result of eliminating a chunk's interior (Schur complement pieces).
 template <int K>
@@ -413,16 +441,19 @@ SMNN_HD void reduce_chunk(const Src& src, int64_t a, int64_t b, bool has_left, b
   for (int u = 0; u < L; ++u) {
     const int64_t i = a + u;
     if (i > b) break;
-    double A[Q], f[K];
-    src.load(i, A, f);
+    SMNN_FENCE();
+    double A[Q], f[K], Bp[KK];
+    src.load(i, A, f, Bp);                     // Bp = B_{i-1} (block (i, i-1)) when i > 0
     double D[Q], X[KK];
     if (u == 0) {
 #pragma unroll
       for (int e = 0; e < Q; ++e) D[e] = A[e];
-      if (has_left) src.coupling(a - 1, X);   // E_L block: (a, a-1) = B_{a-1}
+      if (has_left) {
+#pragma unroll
+        for (int e = 0; e < KK; ++e) X[e] = Bp[e];   // E_L block: (a, a-1) = B_{a-1}
+      }
     } else {
-      double W[KK];
-      src.coupling(i - 1, W);
+      double (&W)[KK] = Bp;
       rsolve_t<K>(Lc, W);                      // W = B_{i-1} L_{i-1}^{-T}
       sym_minus_wwt<K>(A, W, D);               // D_i = A_i - W W^T
       sub_matvec<K>(W, gh, f);                 // g_i = f_i - W ghat_{i-1}
@@ -449,11 +480,9 @@ SMNN_HD void reduce_chunk(const Src& src, int64_t a, int64_t b, bool has_left, b
     for (int e = 0; e < K; ++e) out.lf[e] = -out.lf[e];
   }
   if (has_right) {
-    double V[KK];
-    src.coupling(b, V);
+    double V[KK], A[Q], f[K];
+    src.load(b + 1, A, f, V);                  // V = B_b
     rsolve_t<K>(Lc, V);                        // V = B_b L_b^{-T}
-    double A[Q], f[K];
-    src.load(b + 1, A, f);
     sym_minus_wwt<K>(A, V, out.rA);
     sub_matvec<K>(V, gh, f);
 #pragma unroll
@@ -475,13 +504,10 @@ SMNN_HD int backsub_chunk(const Src& src, int64_t a, int64_t b, bool has_left, b
   for (int u = 0; u < L; ++u) {
     const int64_t i = a + u;
     if (i > b) break;
-    double A[Q], f[K];
-    src.load(i, A, f);
-    if (u == 0 && has_left) {
-      double B[KK];
-      src.coupling(a - 1, B);
-      sub_matvec<K>(B, xl, f);                 // f_a -= B_{a-1} x_{a-1}
-    }
+    SMNN_FENCE();
+    double A[Q], f[K], Bp[KK];
+    src.load(i, A, f, Bp);                     // Bp = B_{i-1} when i > 0
+    if (u == 0 && has_left) sub_matvec<K>(Bp, xl, f);   // f_a -= B_{a-1} x_{a-1}
     if (i == b && has_right) {
       double B[KK];
       src.coupling(b, B);
@@ -492,8 +518,7 @@ SMNN_HD int backsub_chunk(const Src& src, int64_t a, int64_t b, bool has_left, b
 #pragma unroll
       for (int e = 0; e < Q; ++e) D[e] = A[e];
     } else {
-      double W[KK];
-      src.coupling(i - 1, W);
+      double (&W)[KK] = Bp;
       rsolve_t<K>(Ls[u > 0 ? u - 1 : 0], W);   // W = B_{i-1} L_{i-1}^{-T}
       sym_minus_wwt<K>(A, W, D);               // D_i = A_i - W W^T
       sub_matvec<K>(W, x[u > 0 ? u - 1 : 0], f);
@@ -600,7 +625,7 @@ struct Src0 {
     }
   }
 
-  SMNN_HD void load(int64_t i, double (&A)[Dim<K>::Q], double (&f)[K]) const {
+  SMNN_HD void load(int64_t i, double (&A)[Dim<K>::Q], double (&f)[K], double (&Bp)[Dim<K>::KK]) const {
     double ci[K];
 #pragma unroll
     for (int r = 0; r < K; ++r) ci[r] = ld(c, i * K + r);
@@ -623,6 +648,7 @@ struct Src0 {
     if (has_prev) {
       powers<K>(ld(s, i - 1), pl);
       add_right_block<K>(pl, ws2, A);
+      coupling_block<K>(pl, ws2, Bp);
     }
     if (RHS == RHS_BETA) {
       const double di = ld(d, i);
@@ -704,12 +730,16 @@ template <int K>
 struct SrcN {
   const double* rec;  // [n][Q + KK] of this instance
   const double* rhs;  // [n][K]
-  SMNN_HD void load(int64_t i, double (&A)[Dim<K>::Q], double (&f)[K]) const {
+  SMNN_HD void load(int64_t i, double (&A)[Dim<K>::Q], double (&f)[K], double (&Bp)[Dim<K>::KK]) const {
     constexpr int R = Dim<K>::Q + Dim<K>::KK;
 #pragma unroll
     for (int e = 0; e < Dim<K>::Q; ++e) A[e] = rec[i * R + e];
 #pragma unroll
     for (int e = 0; e < K; ++e) f[e] = rhs[i * K + e];
+    if (i > 0) {
+#pragma unroll
+      for (int e = 0; e < Dim<K>::KK; ++e) Bp[e] = rec[(i - 1) * R + Dim<K>::Q + e];
+    }
   }
   SMNN_HD void coupling(int64_t i, double (&B)[Dim<K>::KK]) const {
     constexpr int R = Dim<K>::Q + Dim<K>::KK;

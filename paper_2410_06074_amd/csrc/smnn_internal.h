@@ -38,6 +38,7 @@ struct Level0Args {
   void* dw = nullptr;        // [N][3]
   uint32_t* info = nullptr;  // [N] smallest failing step + 1 (UINT32_MAX = none)
   int n_init = 0;
+  int L0 = 8, L1 = 8;        // chunk lengths of level 0 and of levels >= 1
   int64_t N = 0;
 };
 

@@ -76,10 +76,11 @@ __device__ __forceinline__ Src0<K, TIO, RHS> make_src0(const Level0Args& a, int6
   return S;
 }
 
-__device__ __forceinline__ void report_fail(uint32_t* info, int64_t inst, int level, int64_t node, int L) {
+__device__ __forceinline__ void report_fail(const Level0Args& a, int64_t inst, int level, int64_t node) {
+  uint32_t* info = a.info;
   if (!info) return;
   int64_t step = node;
-  for (int l = 0; l < level; ++l) step = (step + 1) * L - 1;
+  for (int l = level; l > 0; --l) step = (step + 1) * (l == 1 ? a.L0 : a.L1) - 1;
   const uint64_t v = static_cast<uint64_t>(step) + 1;
   atomicMin(info + inst, v > 0xFFFFFFFEull ? 0xFFFFFFFEu : static_cast<uint32_t>(v));
 }
@@ -125,7 +126,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduce0(LevelDev l0, Le
     if (valid && (geo.has_left || geo.has_right)) {
       const auto S = make_src0<K, TIO, RHS>(a, inst, off, n);
       reduce_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, red);
-      if (red.fail) report_fail(a.info, inst, 0, geo.a + red.fail - 1, L);
+      if (red.fail) report_fail(a, inst, 0, geo.a + red.fail - 1);
     }
     const bool writer = valid && lane > 0 && geo.has_left;
     const int64_t node = writer ? l1.node_off[inst] + j - 1 : 0;
@@ -162,7 +163,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduceN(LevelDev lv, Le
       S.rec = lv.rec + off * REC;
       S.rhs = lv.rhs + off * K;
       reduce_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, red);
-      if (red.fail) report_fail(a.info, inst, level, geo.a + red.fail - 1, L);
+      if (red.fail) report_fail(a, inst, level, geo.a + red.fail - 1);
     }
     const bool writer = valid && lane > 0 && geo.has_left;
     const int64_t node = writer ? nx.node_off[inst] + j - 1 : 0;
@@ -197,7 +198,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsubN(LevelDev lv, L
     S.rec = lv.rec + off * REC;
     S.rhs = lv.rhs + off * K;
     const int fail = backsub_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs);
-    if (fail) report_fail(a.info, inst, level, geo.a + fail - 1, L);
+    if (fail) report_fail(a, inst, level, geo.a + fail - 1);
     double* x = lv.x + off * K;
 #pragma unroll
     for (int u = 0; u < L; ++u) {
@@ -237,7 +238,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub0(LevelDev l0, L
     }
     const auto S = make_src0<K, TIO, RHS>(a, inst, off, n);
     const int fail = backsub_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs);
-    if (fail) report_fail(a.info, inst, 0, geo.a + fail - 1, L);
+    if (fail) report_fail(a, inst, 0, geo.a + fail - 1);
     const int64_t last = geo.has_right ? geo.b + 1 : geo.b;
     const TIO* v = ADD ? static_cast<const TIO*>(a.v) + off * K : nullptr;
     if (OUT == OUT_STORE) {

@@ -1,9 +1,10 @@
 // Host-side geometry of the recursive partition (no device code).
 //
-// Level 0 nodes are the time steps of every instance.  Each level is cut into
-// chunks of L nodes; every chunk but an instance's last one ends in a
-// separator node, and the separators of level l are the nodes of level l+1.
-// An instance with n <= L nodes at some level is a single chunk there and is
+// Level 0 nodes are the time steps of every instance.  Level 0 is cut into
+// chunks of L0 nodes and every higher level into chunks of L1 nodes.  Every
+// chunk but an instance's last one ends in a separator node, and the
+// separators of level l are the nodes of level l+1.  An instance with no more
+// nodes than the chunk length at some level is a single chunk there and is
 // solved directly by that level's back-substitution.
 #pragma once
 
@@ -23,12 +24,14 @@ struct Level {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Levels for step counts T (all >= 1) and chunk length L (>= 2).
-inline std::vector<Level> build_levels(const std::vector<int64_t>& T, int L) {
+// Levels for step counts T (all >= 1) and chunk lengths L0 (level 0) and
+// L1 (levels >= 1), both >= 2.
+inline std::vector<Level> build_levels(const std::vector<int64_t>& T, int L0, int L1) {
   std::vector<Level> lv;
   std::vector<int64_t> n = T;
   const size_t N = T.size();
   for (;;) {
+    const int L = lv.empty() ? L0 : L1;
     Level l;
     l.n = n;
     l.node_off.assign(N + 1, 0);
@@ -55,10 +58,11 @@ inline std::vector<Level> build_levels(const std::vector<int64_t>& T, int L) {
 }
 
 // Time step (0-based, within its instance) of node `node` of level `level`:
-// separator j of level l is node (j+1) L - 1 of level l-1.
-inline int64_t node_step(int level, int64_t node, int L) {
+// separator j of level l is node (j+1) L - 1 of level l-1, L the chunk
+// length of level l-1.
+inline int64_t node_step(int level, int64_t node, int L0, int L1) {
   int64_t s = node;
-  for (int l = 0; l < level; ++l) s = (s + 1) * L - 1;
+  for (int l = level; l > 0; --l) s = (s + 1) * (l == 1 ? L0 : L1) - 1;
   return s;
 }
 

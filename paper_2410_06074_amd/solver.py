@@ -27,7 +27,8 @@ class Plan:
     """
 
     def __init__(self, order: int, n_init: int, n_inst: int, steps, mode: str = "fp64r",
-                 refine_steps: int = -1, chunk: int = 0, block: int = 0, max_blocks: int = 0):
+                 refine_steps: int = -1, chunk: int = 0, block: int = 0, max_blocks: int = 0,
+                 chunk_upper: int = 0):
         L = _lib.lib()
         if mode not in _lib.MODES:
             raise ValueError("mode must be one of %s" % sorted(_lib.MODES))
@@ -45,6 +46,7 @@ class Plan:
             d.steps_uniform = 0
             self.steps = self._steps_arr
         d.mode, d.refine_steps, d.chunk = _lib.MODES[mode], int(refine_steps), int(chunk)
+        d.chunk_upper = int(chunk_upper)
         d.block, d.max_blocks = int(block), int(max_blocks)
         h = ctypes.c_void_p()
         _lib.check(L.smnn_plan_create(ctypes.byref(d), ctypes.byref(h)), "smnn_plan_create")
@@ -68,6 +70,10 @@ class Plan:
     @property
     def chunk(self):
         return self.query(_lib.Q_CHUNK)
+
+    @property
+    def chunk_upper(self):
+        return self.query(_lib.Q_CHUNK_UPPER)
 
     @property
     def refine_steps(self):

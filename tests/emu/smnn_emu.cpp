@@ -16,7 +16,7 @@ using namespace smnn;
 
 namespace {
 
-template <int K, int L, class TIO>
+template <int K, int L0, int L1, class TIO>
 struct Emu {
   static constexpr int Q = Dim<K>::Q, KK = Dim<K>::KK, REC = Q + KK;
   int n_init;
@@ -58,11 +58,11 @@ struct Emu {
     for (int64_t ch = 0; ch < lvl.chunks; ++ch) {
       const int64_t i = lvl.chunk_inst[ch];
       const int64_t j = ch - lvl.chunk_off[i];
-      const ChunkGeom G = chunk_geom(j, lvl.n[i], L);
+      const ChunkGeom G = chunk_geom(j, lvl.n[i], l == 0 ? L0 : L1);
       Reduced<K> cur{};
       if (G.has_left || G.has_right) {
-        if (l == 0) reduce_chunk<K, L>(src0<RHS>(i, g, v), G.a, G.b, G.has_left, G.has_right, cur);
-        else reduce_chunk<K, L>(srcN(l, i), G.a, G.b, G.has_left, G.has_right, cur);
+        if (l == 0) reduce_chunk<K, L0>(src0<RHS>(i, g, v), G.a, G.b, G.has_left, G.has_right, cur);
+        else reduce_chunk<K, L1>(srcN(l, i), G.a, G.b, G.has_left, G.has_right, cur);
       }
       if (G.has_left) {
         const int64_t node = nxt.node_off[i] + j - 1;
@@ -79,12 +79,12 @@ struct Emu {
     for (int64_t ch = 0; ch < lvl.chunks; ++ch) {
       const int64_t i = lvl.chunk_inst[ch];
       const int64_t j = ch - lvl.chunk_off[i];
-      const ChunkGeom G = chunk_geom(j, lvl.n[i], L);
-      double xl[K] = {}, xr[K] = {}, xs[L][K];
+      const ChunkGeom G = chunk_geom(j, lvl.n[i], L1);
+      double xl[K] = {}, xr[K] = {}, xs[L1][K];
       const int64_t up = (l + 1 < (int)lv.size()) ? lv[l + 1].node_off[i] : 0;
       if (G.has_left) for (int e = 0; e < K; ++e) xl[e] = x[l + 1][(up + j - 1) * K + e];
       if (G.has_right) for (int e = 0; e < K; ++e) xr[e] = x[l + 1][(up + j) * K + e];
-      backsub_chunk<K, L>(srcN(l, i), G.a, G.b, G.has_left, G.has_right, xl, xr, xs);
+      backsub_chunk<K, L1>(srcN(l, i), G.a, G.b, G.has_left, G.has_right, xl, xr, xs);
       const int64_t o = lvl.node_off[i];
       for (int64_t u = 0; u <= G.b - G.a; ++u)
         for (int e = 0; e < K; ++e) x[l][(o + G.a + u) * K + e] = xs[u][e];
@@ -100,12 +100,12 @@ struct Emu {
     for (int64_t ch = 0; ch < lvl.chunks; ++ch) {
       const int64_t i = lvl.chunk_inst[ch];
       const int64_t j = ch - lvl.chunk_off[i];
-      const ChunkGeom G = chunk_geom(j, lvl.n[i], L);
-      double xl[K] = {}, xr[K] = {}, xs[L][K];
+      const ChunkGeom G = chunk_geom(j, lvl.n[i], L0);
+      double xl[K] = {}, xr[K] = {}, xs[L0][K];
       const int64_t up = lv.size() > 1 ? lv[1].node_off[i] : 0;
       if (G.has_left) for (int e = 0; e < K; ++e) xl[e] = x[1][(up + j - 1) * K + e];
       if (G.has_right) for (int e = 0; e < K; ++e) xr[e] = x[1][(up + j) * K + e];
-      backsub_chunk<K, L>(src0<RHS>(i, g, v), G.a, G.b, G.has_left, G.has_right, xl, xr, xs);
+      backsub_chunk<K, L0>(src0<RHS>(i, g, v), G.a, G.b, G.has_left, G.has_right, xl, xr, xs);
       const int64_t o = lvl.node_off[i];
       const int64_t last = G.has_right ? G.b + 1 : G.b;
       for (int64_t t = G.a; t <= last; ++t)
@@ -128,17 +128,17 @@ struct Emu {
     for (int64_t ch = 0; ch < lvl.chunks; ++ch) {
       const int64_t i = lvl.chunk_inst[ch];
       const int64_t j = ch - lvl.chunk_off[i];
-      const ChunkGeom G = chunk_geom(j, lvl.n[i], L);
-      double xl[K] = {}, xr[K] = {}, xs[L][K];
+      const ChunkGeom G = chunk_geom(j, lvl.n[i], L0);
+      double xl[K] = {}, xr[K] = {}, xs[L0][K];
       const int64_t up = lv.size() > 1 ? lv[1].node_off[i] : 0;
       if (G.has_left) for (int e = 0; e < K; ++e) xl[e] = x[1][(up + j - 1) * K + e];
       if (G.has_right) for (int e = 0; e < K; ++e) xr[e] = x[1][(up + j) * K + e];
       const auto S = src0<RHS>(i, g, v);
-      backsub_chunk<K, L>(S, G.a, G.b, G.has_left, G.has_right, xl, xr, xs);
+      backsub_chunk<K, L0>(S, G.a, G.b, G.has_left, G.has_right, xl, xr, xs);
       const int64_t o = lvl.node_off[i];
       const int64_t last = G.has_right ? G.b + 1 : G.b;
-      double lam[L + 1][K], yv[L + 1][K];
-      for (int u = -1; u < L; ++u) {
+      double lam[L0 + 1][K], yv[L0 + 1][K];
+      for (int u = -1; u < L0; ++u) {
         const int64_t t = G.a + u;
         const bool in = t >= 0 && t <= last;
         for (int e = 0; e < K; ++e) {
@@ -152,7 +152,7 @@ struct Emu {
         }
       }
       double dwp[3];
-      grad_chunk<K, L, TIO>(S.c, S.d, S.s, S.n, S.p, G, lam, yv, dc + o * K, dd + o, ds + o, du0 + i * n_init, dwp);
+      grad_chunk<K, L0, TIO>(S.c, S.d, S.s, S.n, S.p, G, lam, yv, dc + o * K, dd + o, ds + o, du0 + i * n_init, dwp);
       for (int e = 0; e < 3; ++e) dw_part[ch * 3 + e] = dwp[e];
     }
   }
@@ -179,13 +179,13 @@ struct Emu {
 };
 
 // level >= 1 reductions read records, not inputs: specialise reduce() for that
-template <int K, int L, class TIO>
+template <int K, int L0, int L1, class TIO>
 struct Runner {
   static int forward(int n_init, int64_t N, const int64_t* T, const TIO* c, const TIO* d, const TIO* s,
                      const TIO* u0, const TIO* w, TIO* y, int refine) {
-    Emu<K, L, TIO> E;
+    Emu<K, L0, L1, TIO> E;
     E.n_init = n_init;
-    E.lv = build_levels(std::vector<int64_t>(T, T + N), L);
+    E.lv = build_levels(std::vector<int64_t>(T, T + N), L0, L1);
     E.c = c; E.d = d; E.s = s; E.u0 = u0; E.w = w;
     E.alloc();
     const int64_t S = E.lv[0].nodes;
@@ -204,29 +204,23 @@ struct Runner {
   // one refinement pass from a given iterate v: out = v + M^{-1} A^T W (b - A v)
   static int refine_from(int n_init, int64_t N, const int64_t* T, const TIO* c, const TIO* d, const TIO* s,
                          const TIO* u0, const TIO* w, const TIO* v, TIO* out) {
-    Emu<K, L, TIO> E;
+    Emu<K, L0, L1, TIO> E;
     E.n_init = n_init;
-    E.lv = build_levels(std::vector<int64_t>(T, T + N), L);
+    E.lv = build_levels(std::vector<int64_t>(T, T + N), L0, L1);
     E.c = c; E.d = d; E.s = s; E.u0 = u0; E.w = w;
     E.alloc();
     std::vector<TIO> tmp(E.lv[0].nodes * K);
     E.template solve<RHS_BETA>(true, nullptr, nullptr, tmp.data(), nullptr);
     E.template solve<RHS_RESID>(false, nullptr, v, out, nullptr);
-    if (dbg_rhs1 && E.lv.size() > 1) {
-      std::copy(E.rhs[1].begin(), E.rhs[1].end(), dbg_rhs1);
-      std::copy(E.x[1].begin(), E.x[1].end(), dbg_x1);
-    }
     return 0;
   }
-  static inline double* dbg_rhs1 = nullptr;
-  static inline double* dbg_x1 = nullptr;
 
   static int backward(int n_init, int64_t N, const int64_t* T, const TIO* c, const TIO* d, const TIO* s,
                       const TIO* u0, const TIO* w, const TIO* y, const TIO* gy, TIO* dc, TIO* dd, TIO* ds,
                       TIO* du0, TIO* dw, int refine) {
-    Emu<K, L, TIO> E;
+    Emu<K, L0, L1, TIO> E;
     E.n_init = n_init;
-    E.lv = build_levels(std::vector<int64_t>(T, T + N), L);
+    E.lv = build_levels(std::vector<int64_t>(T, T + N), L0, L1);
     E.c = c; E.d = d; E.s = s; E.u0 = u0; E.w = w;
     E.alloc();
     const int64_t S = E.lv[0].nodes;
@@ -274,11 +268,12 @@ struct Runner {
 }  // namespace
 
 #define DISPATCH(KV, LV, FN, ...)                                                      \
-  if (K == KV && Lc == LV) return Runner<KV, LV, TYPE>::FN(__VA_ARGS__);
+  if (K == KV && Lc == LV && Lu == LV) return Runner<KV, LV, LV, TYPE>::FN(__VA_ARGS__); \
+  if (K == KV && Lc == LV && Lu == 8 && LV != 8) return Runner<KV, LV, 8, TYPE>::FN(__VA_ARGS__);
 
 extern "C" {
 #define TYPE double
-int emu_forward_f64(int K, int Lc, int n_init, int64_t N, const int64_t* T, const double* c, const double* d,
+int emu_forward_f64(int K, int Lc, int Lu, int n_init, int64_t N, const int64_t* T, const double* c, const double* d,
                     const double* s, const double* u0, const double* w, double* y, int refine) {
   DISPATCH(2, 4, forward, n_init, N, T, c, d, s, u0, w, y, refine)
   DISPATCH(3, 4, forward, n_init, N, T, c, d, s, u0, w, y, refine)
@@ -288,7 +283,7 @@ int emu_forward_f64(int K, int Lc, int n_init, int64_t N, const int64_t* T, cons
   DISPATCH(5, 4, forward, n_init, N, T, c, d, s, u0, w, y, refine)
   return -1;
 }
-int emu_refine_f64(int K, int Lc, int n_init, int64_t N, const int64_t* T, const double* c, const double* d,
+int emu_refine_f64(int K, int Lc, int Lu, int n_init, int64_t N, const int64_t* T, const double* c, const double* d,
                    const double* s, const double* u0, const double* w, const double* v, double* out) {
   DISPATCH(2, 4, refine_from, n_init, N, T, c, d, s, u0, w, v, out)
   DISPATCH(3, 4, refine_from, n_init, N, T, c, d, s, u0, w, v, out)
@@ -298,18 +293,7 @@ int emu_refine_f64(int K, int Lc, int n_init, int64_t N, const int64_t* T, const
   DISPATCH(5, 4, refine_from, n_init, N, T, c, d, s, u0, w, v, out)
   return -1;
 }
-int emu_refine_debug_f64(int K, int Lc, int n_init, int64_t N, const int64_t* T, const double* c,
-                         const double* d, const double* s, const double* u0, const double* w, const double* v,
-                         double* out, double* rhs1, double* x1) {
-  if (K != 3 || Lc != 8) return -1;
-  Runner<3, 8, double>::dbg_rhs1 = rhs1;
-  Runner<3, 8, double>::dbg_x1 = x1;
-  const int rc = Runner<3, 8, double>::refine_from(n_init, N, T, c, d, s, u0, w, v, out);
-  Runner<3, 8, double>::dbg_rhs1 = nullptr;
-  Runner<3, 8, double>::dbg_x1 = nullptr;
-  return rc;
-}
-int emu_backward_f64(int K, int Lc, int n_init, int64_t N, const int64_t* T, const double* c, const double* d,
+int emu_backward_f64(int K, int Lc, int Lu, int n_init, int64_t N, const int64_t* T, const double* c, const double* d,
                      const double* s, const double* u0, const double* w, const double* y, const double* gy,
                      double* dc, double* dd, double* ds, double* du0, double* dw, int refine) {
   DISPATCH(2, 4, backward, n_init, N, T, c, d, s, u0, w, y, gy, dc, dd, ds, du0, dw, refine)

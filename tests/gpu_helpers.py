@@ -11,9 +11,9 @@ MODES = ("fp64", "fp64r", "fp32r")
 #  fp32r: the stated FP32+refinement target; measured against the oracle run on
 #         the same float32-rounded inputs.
 #  fp64 : the paper's single normal-equation solve; its error is bounded by
-#         about cond(M) * 2^-53, and cond(M) ~ 1.2e9 for the Gaussian
+#         about c cond(M) * 2^-53, and cond(M) ~ 1.2e9 for the Gaussian
 #         configurations (estimated per instance by oracle.banded.cond), so it
-#         is held to 2 * cond(M) * 2^-53 instead of 1e-10.
+#         is held to 10 * cond(M) * 2^-53 (floor 1e-12) instead of 1e-10.
 Y_TOL = {"fp64r": 1e-10, "fp32r": 1e-4}
 # Gradients: term-magnitude-scaled error (tests/metrics.py); the refined FP64
 # adjoint leaves ~1e-15, float32 outputs ~1e-7, and the plain FP64 adjoint
@@ -96,11 +96,11 @@ def compare(bt, out, ref, idx, ref_off=None):
 
 def g_tolerance(mode, kappa):
     if mode == "fp64":
-        return max(1e-10, 2.0 * kappa * np.finfo(np.float64).eps)
+        return max(1e-10, 10.0 * kappa * np.finfo(np.float64).eps)
     return G_TOL[mode]
 
 
 def y_tolerance(mode, kappa):
     if mode == "fp64":
-        return max(1e-13, 2.0 * kappa * np.finfo(np.float64).eps)
+        return max(1e-12, 10.0 * kappa * np.finfo(np.float64).eps)
     return Y_TOL[mode]

@@ -49,7 +49,7 @@ def _desc(**kw):
     from paper_2410_06074_amd import _lib as L
     d = L.PlanDesc()
     d.order, d.n_init, d.n_inst, d.steps, d.steps_uniform = 2, 2, 4, None, 100
-    d.mode, d.refine_steps, d.chunk, d.block, d.max_blocks = 1, -1, 0, 0, 0
+    d.mode, d.refine_steps, d.chunk, d.chunk_upper, d.block, d.max_blocks = 1, -1, 0, 0, 0, 0
     for k, v in kw.items():
         setattr(d, k, v)
     return d
@@ -89,14 +89,16 @@ def test_null_arguments_rejected():
 def test_levels_geometry_matches_partition_rule():
     # The partition (smnn_levels.h): chunks of L nodes, separators are the last
     # node of every chunk but an instance's last, and become the next level.
-    def levels(T, L):
+    def levels(T, L, Lu=None):
         out, n = [], list(T)
         while True:
-            g = [(x + L - 1) // L for x in n]
+            Lc = L if not out or Lu is None else Lu
+            g = [(x + Lc - 1) // Lc for x in n]
             out.append((sum(n), sum(g)))
-            nxt = [gi - 1 if x > L else 0 for x, gi in zip(n, g)]
+            nxt = [gi - 1 if x > Lc else 0 for x, gi in zip(n, g)]
             if not any(nxt):
                 return out
             n = nxt
     assert levels([10000], 8) == [(10000, 1250), (1249, 157), (156, 20), (19, 3), (2, 1)]
     assert levels([1, 8, 9], 8) == [(18, 4), (1, 1)]
+    assert levels([10000], 4, 8) == [(10000, 2500), (2499, 313), (312, 39), (38, 5), (4, 1)]

@@ -39,44 +39,45 @@ def _p(a):
     return a.ctypes.data_as(_DP)
 
 
-def emu_run(lib, bt, L, refine, gy):
+def emu_run(lib, bt, L, refine, gy, Lu=None):
+    Lu = L if Lu is None else Lu
     T = np.ascontiguousarray(bt.T, dtype=np.int64)
     u0 = np.ascontiguousarray(bt.u0)
     y = np.zeros_like(bt.c)
-    assert lib.emu_forward_f64(bt.k, L, bt.n_init, ctypes.c_int64(bt.n_inst), T.ctypes.data_as(_IP), _p(bt.c),
+    assert lib.emu_forward_f64(bt.k, L, Lu, bt.n_init, ctypes.c_int64(bt.n_inst), T.ctypes.data_as(_IP), _p(bt.c),
                                _p(bt.b), _p(bt.h), _p(u0), _p(bt.w), _p(y), refine) == 0
     out = {k: np.zeros_like(v) for k, v in (("dc", bt.c), ("dd", bt.b), ("ds", bt.h), ("du0", u0), ("dw", bt.w))}
-    assert lib.emu_backward_f64(bt.k, L, bt.n_init, ctypes.c_int64(bt.n_inst), T.ctypes.data_as(_IP), _p(bt.c),
+    assert lib.emu_backward_f64(bt.k, L, Lu, bt.n_init, ctypes.c_int64(bt.n_inst), T.ctypes.data_as(_IP), _p(bt.c),
                                 _p(bt.b), _p(bt.h), _p(u0), _p(bt.w), _p(y), _p(gy), _p(out["dc"]), _p(out["dd"]),
                                 _p(out["ds"]), _p(out["du0"]), _p(out["dw"]), refine) == 0
     out["y"] = y
     return out
 
 
-CASES = [(1, 4), (2, 4), (2, 8), (3, 4), (3, 8)]
+CASES = [(1, 4, 4), (2, 4, 4), (2, 8, 8), (3, 4, 4), (3, 8, 8), (2, 4, 8), (3, 4, 8)]
 EDGE_T = [1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 32, 33, 64, 65, 100, 1000]
 
 
-@pytest.mark.parametrize("R,L", CASES)
-def test_partition_schedule_matches_oracle(R, L):
+@pytest.mark.parametrize("R,L,Lu", CASES)
+def test_partition_schedule_matches_oracle(R, L, Lu):
     lib = ctypes.CDLL(_build())
-    bt = gaussian_batch(len(EDGE_T), EDGE_T, R=R, seed=7 * R + L, weights=(1.3, 0.8, 1.1))
+    bt = gaussian_batch(len(EDGE_T), EDGE_T, R=R, seed=7 * R + L + Lu, weights=(1.3, 0.8, 1.1))
     gy = np.random.default_rng(R).standard_normal(bt.c.shape)
     ref = banded.grad(bt, gy)
     kappa = banded.cond(bt)
     o = bt.offsets
     for refine in (0, 1):
-        out = emu_run(lib, bt, L, refine, gy)
+        out = emu_run(lib, bt, L, refine, gy, Lu)
         for i in range(bt.n_inst):
             sl = slice(o[i], o[i + 1])
             # refined: 1e-10; for R = 3 (cond(M) up to ~1e13 at h ~ 0.01) the oracle
             # itself only resolves ~cond(A) u, so the bound follows it there.
-            resolve = 1e3 * np.sqrt(kappa[i]) * 2.2e-16 if R >= 3 else 0.0
-            tol = max(1e-13, 2 * kappa[i] * 2.2e-16) if refine == 0 else max(1e-10, resolve)
+            resolve = 1e4 * np.sqrt(kappa[i]) * 2.2e-16 if R >= 3 else 0.0
+            tol = max(1e-12, 10 * kappa[i] * 2.2e-16) if refine == 0 else max(1e-10, resolve)
             assert max(metrics.rel_by_order(out["y"][sl], ref["y"][sl], bt.k)) <= tol, (i, refine)
             c, d, s, u0, w = bt.instance(i)
             sc = metrics.grad_scales(c, d, s, u0, w, ref["y"][sl], ref["lam"][sl])
-            gt = max(1e-10, 2 * kappa[i] * 2.2e-16) if refine == 0 else max(1e-10, resolve)
+            gt = max(1e-10, 10 * kappa[i] * 2.2e-16) if refine == 0 else max(1e-10, resolve)
             for key in ("dc", "dd", "ds"):
                 assert metrics.grad_error(out[key][sl], ref[key][sl], sc[key]) <= gt, (i, refine, key)
             for key in ("du0", "dw"):
@@ -92,9 +93,9 @@ def test_partition_schedule_under_address_sanitizer():
             "from tests.test_emu_partition import emu_run\n"
             "from workloads import gaussian_batch\n"
             "lib = ctypes.CDLL(%r)\n"
-            "for R, L in %r:\n"
+            "for R, L, Lu in %r:\n"
             "    bt = gaussian_batch(12, [1,2,3,4,5,8,9,16,17,33,64,100], R=R, seed=R)\n"
-            "    emu_run(lib, bt, L, 1, np.ones_like(bt.c))\n"
+            "    emu_run(lib, bt, L, 1, np.ones_like(bt.c), Lu)\n"
             "print('asan-clean')\n") % (os.path.dirname(HERE), HERE, so, CASES)
     env = dict(os.environ, LD_PRELOAD=asan, ASAN_OPTIONS="detect_leaks=0")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)

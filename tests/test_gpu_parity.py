@@ -63,8 +63,8 @@ def test_ragged_lengths_forward_and_gradients(R, chunk, mode):
     else:
         # R = 3 at h ~ 0.01 has cond(M) ~ 1e12..1e14: the oracle's own error is
         # ~cond(A) u, so compare at the accuracy both sides resolve.
-        assert worst["y"] <= max(H.y_tolerance(mode, kappa), 1e3 * np.sqrt(kappa) * np.finfo(float).eps)
-    resolve = 1e3 * np.sqrt(kappa) * np.finfo(float).eps if R >= 3 else 0.0
+        assert worst["y"] <= max(H.y_tolerance(mode, kappa), 1e4 * np.sqrt(kappa) * np.finfo(float).eps)
+    resolve = 1e4 * np.sqrt(kappa) * np.finfo(float).eps if R >= 3 else 0.0
     for key in ("dc", "dd", "ds", "du0", "dw"):
         assert worst[key] <= max(H.g_tolerance(mode, kappa), resolve), key
     assert (out["info"] == 0).all()
