@@ -88,7 +88,7 @@ def describe(name, bt, mode):
 
 
 # --------------------------------------------------------------- GPU run
-def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0):
+def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0, graph=True, tune=False):
     import numpy as np
     import torch
     from paper_2410_06074_amd import Plan
@@ -99,9 +99,19 @@ def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0):
     dt = torch.float32 if mode == "fp32r" else torch.float64
     io = 4 if mode == "fp32r" else 8
     steps_arg = int(bt.T[0]) if (bt.T == bt.T[0]).all() else bt.T
-    plan = Plan(bt.R, bt.n_init, bt.n_inst, steps_arg, mode=mode, chunk=chunk, chunk_upper=chunk_upper)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt)
     c, b, h, u0, w = t(bt.c), t(bt.b), t(bt.h), t(bt.u0), t(bt.w)
+    tuned = None
+    block = max_blocks = 0
+    if tune:
+        from paper_2410_06074_amd import autotune
+        gy0 = torch.ones_like(c)
+        tuned = autotune(bt.R, bt.n_init, bt.n_inst, steps_arg, mode, c, b, h, u0, w, gy0, iters=2)
+        chunk, chunk_upper = tuned["chunk"], tuned["chunk_upper"]
+        block, max_blocks = tuned["block"], tuned["max_blocks"]
+        log("  autotuned:", {k: v for k, v in tuned.items() if k != "candidates"})
+    plan = Plan(bt.R, bt.n_init, bt.n_inst, steps_arg, mode=mode, chunk=chunk, chunk_upper=chunk_upper,
+                block=block, max_blocks=max_blocks)
     S, K = plan.total_steps, plan.k
     y = torch.empty((S, K), dtype=dt, device=dev)
     fac, ws = plan.new_factor(dev), plan.new_workspace(dev)
@@ -125,7 +135,21 @@ def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0):
         step()
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
+    ms_eager = e0.elapsed_time(e1) / steps
+    ms = ms_eager
+    if graph:
+        # the whole forward+backward launch sequence as one hipGraph replay
+        from paper_2410_06074_amd import CapturedSolve
+        cap = CapturedSolve(plan, c, b, h, u0, w, y, fac, ws, gy=gy, grads=(dc, db, dh, du0, dw))
+        for _ in range(warmup):
+            cap.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            cap.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
 
     # traced copy of the timed steps: one event pair around every launch
     launches_per_step = 64 * max(1, len(plan.levels))
@@ -158,7 +182,7 @@ def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0):
     err = 0.0
     for j, i in enumerate(sample_idx):
         err = max(err, max(metrics.rel_by_order(yn[o[i]:o[i + 1]], ref[so[j]:so[j + 1]], K)))
-    return {"plan": plan, "ms": ms, "ms_traced": ms_traced, "per_kind": per_kind, "step_bytes": step_bytes,
+    return {"plan": plan, "ms": ms, "ms_eager": ms_eager, "graph": graph, "tuned": tuned, "ms_traced": ms_traced, "per_kind": per_kind, "step_bytes": step_bytes,
             "err": err, "levels": plan.levels, "chunk": [plan.chunk, plan.chunk_upper], "refine": plan.refine_steps}
 
 
@@ -207,6 +231,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--chunk", type=int, default=0, help="time steps per lane at level 0 (0: library default)")
     ap.add_argument("--chunk-upper", type=int, default=0, help="nodes per lane at levels >= 1 (0: default)")
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of hipGraph replays")
+    ap.add_argument("--autotune", action="store_true", help="pick the launch mapping with smnn_autotune first")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solve is per-instance independent and this build has no "
@@ -227,10 +253,11 @@ def main():
     for m in modes:
         log("mode", m)
         results[m] = run_mode(bt, m, args.steps, args.warmup, sample, chunk=args.chunk,
-                              chunk_upper=args.chunk_upper)
+                              chunk_upper=args.chunk_upper, graph=not args.no_graph, tune=args.autotune)
         r = results[m]
-        log("  %.3f ms/step (traced %.3f), %.3e steps/s, err %.2e, levels %s"
-            % (r["ms"], r["ms_traced"], bt.total_steps / (r["ms"] * 1e-3), r["err"], r["levels"]))
+        log("  %.3f ms/step (eager %.3f, traced %.3f), %.3e steps/s, err %.2e, chunk %s, levels %s"
+            % (r["ms"], r["ms_eager"], r["ms_traced"], bt.total_steps / (r["ms"] * 1e-3), r["err"], r["chunk"],
+               r["levels"]))
     head = results[args.mode]
     value = bt.total_steps / (head["ms"] * 1e-3)
     line = {
@@ -253,7 +280,8 @@ def main():
         "step_bandwidth_frac": round(head["step_bytes"] / (head["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "modes": {m: {"steps_per_s": round(bt.total_steps / (r["ms"] * 1e-3), 1), "ms_per_step": round(r["ms"], 5),
                       "err_vs_fp64_oracle": r["err"], "refine_steps": r["refine"], "chunk": r["chunk"],
-                      "roofline_frac": roofline(r)["frac"],
+                      "roofline_frac": roofline(r)["frac"], "eager_ms_per_step": round(r["ms_eager"], 5),
+                      "timing": "hipGraph replay" if r["graph"] else "eager launches",
                       "step_bandwidth_frac": round(r["step_bytes"] / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                       "traced_ms_per_step": round(r["ms_traced"], 5)}
                   for m, r in results.items()},

@@ -174,6 +174,24 @@ typedef struct {
 smnn_status smnn_trace_enable(smnn_plan* plan, int32_t capacity);
 int32_t smnn_trace_read(smnn_plan* plan, smnn_trace_record* out, int32_t cap);
 
+/* Autotuner.  Times smnn_forward + smnn_backward on the caller's inputs for
+ * candidate launch mappings of `desc` -- chunk lengths (level 0 and the
+ * separator levels), workgroup size and persistent grid size -- by a
+ * coordinate search, and returns the fastest in *best (fields chunk,
+ * chunk_upper, block, max_blocks; ms = mean time of one forward+backward).
+ * Every candidate visited is written to all[0 .. *n_all-1] (up to cap).
+ * Inputs are device arrays in desc's layout and element type; gy is dl/dy.
+ * Unlike the solve calls this one allocates (temporary device buffers) and
+ * synchronises `stream`; run it once, before capture, and create the plan
+ * with the returned fields. */
+typedef struct {
+  int32_t chunk, chunk_upper, block, max_blocks;
+  float ms;
+} smnn_tune_result;
+smnn_status smnn_autotune(const smnn_plan_desc* desc, const void* c, const void* b, const void* h,
+                          const void* u0, const void* w, const void* gy, int32_t iters, void* stream,
+                          smnn_tune_result* best, smnn_tune_result* all, int32_t cap, int32_t* n_all);
+
 /* Static description of a status code. */
 const char* smnn_status_string(smnn_status status);
 

@@ -6,5 +6,7 @@ include/smnn.h, with a thin Python binding.
 """
 from ._lib import SmnnError, lib  # noqa: F401
 from .solver import Plan, SmnnSolve, get_plan, solve  # noqa: F401
+from .graph import CapturedSolve  # noqa: F401
+from .tune import autotune  # noqa: F401
 
-__all__ = ["Plan", "SmnnSolve", "SmnnError", "get_plan", "solve", "lib"]
+__all__ = ["Plan", "SmnnSolve", "SmnnError", "CapturedSolve", "autotune", "get_plan", "solve", "lib"]

@@ -30,6 +30,11 @@ class TraceRecord(ctypes.Structure):
 KERNEL_NAMES = {1: "reduce0", 2: "reduceN", 3: "backsubN", 4: "backsub0", 5: "dw_reduce", 6: "info"}
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("chunk_upper", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("max_blocks", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+
 class PlanDesc(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("n_init", ctypes.c_int32), ("n_inst", ctypes.c_int64),
                 ("steps", ctypes.POINTER(ctypes.c_int64)), ("steps_uniform", ctypes.c_int64),
@@ -64,6 +69,10 @@ def lib():
         L.smnn_trace_enable.restype = ctypes.c_int
         L.smnn_trace_read.argtypes = [vp, ctypes.POINTER(TraceRecord), ctypes.c_int32]
         L.smnn_trace_read.restype = ctypes.c_int32
+        L.smnn_autotune.argtypes = [ctypes.POINTER(PlanDesc)] + [vp] * 6 + [ctypes.c_int32, vp,
+                                    ctypes.POINTER(TuneResult), ctypes.POINTER(TuneResult), ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_int32)]
+        L.smnn_autotune.restype = ctypes.c_int
         L.smnn_status_string.argtypes = [ctypes.c_int]
         L.smnn_status_string.restype = ctypes.c_char_p
         _lib = L

@@ -371,6 +371,110 @@ smnn_status smnn_backward(const smnn_plan* p, const void* c, const void* b, cons
   return SMNN_OK;
 }
 
+namespace {
+
+// Time one candidate: mean ms of forward + backward over `iters` calls.
+smnn_status time_candidate(const smnn_plan_desc& d, const void* c, const void* b, const void* h, const void* u0,
+                           const void* w, const void* gy, int iters, hipStream_t st, float* ms) {
+  smnn_plan* p = nullptr;
+  smnn_status s = smnn_plan_create(&d, &p);
+  if (s != SMNN_OK) return s;
+  const size_t io = p->f32 ? sizeof(float) : sizeof(double);
+  const size_t S = static_cast<size_t>(p->S), K = static_cast<size_t>(p->K), N = static_cast<size_t>(p->N);
+  void *y = nullptr, *fac = nullptr, *ws = nullptr, *dc = nullptr, *db = nullptr, *dh = nullptr, *du0 = nullptr,
+       *dw = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    for (void* q : {y, fac, ws, dc, db, dh, du0, dw})
+      if (q) (void)hipFree(q);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    smnn_plan_destroy(p);
+  };
+  if (hipMalloc(&y, io * S * K) != hipSuccess || hipMalloc(&fac, p->factor_bytes) != hipSuccess ||
+      hipMalloc(&ws, p->workspace_bytes) != hipSuccess || hipMalloc(&dc, io * S * K) != hipSuccess ||
+      hipMalloc(&db, io * S) != hipSuccess || hipMalloc(&dh, io * S) != hipSuccess ||
+      hipMalloc(&du0, io * (N * p->n_init + 1)) != hipSuccess || hipMalloc(&dw, io * N * 3) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return SMNN_ERR_HIP;
+  }
+  auto step = [&]() -> smnn_status {
+    smnn_status r = smnn_forward(p, c, b, h, u0, w, y, fac, p->factor_bytes, ws, p->workspace_bytes, nullptr, st);
+    if (r != SMNN_OK) return r;
+    return smnn_backward(p, c, b, h, u0, w, y, fac, p->factor_bytes, gy, dc, db, dh, du0, dw, ws,
+                         p->workspace_bytes, nullptr, st);
+  };
+  s = step();  // warm-up
+  if (s == SMNN_OK && hipEventRecord(e0, st) != hipSuccess) s = SMNN_ERR_HIP;
+  for (int it = 0; it < iters && s == SMNN_OK; ++it) s = step();
+  if (s == SMNN_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                       hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+    s = SMNN_ERR_HIP;
+  if (s == SMNN_OK) *ms /= static_cast<float>(iters);
+  cleanup();
+  return s;
+}
+
+}  // namespace
+
+smnn_status smnn_autotune(const smnn_plan_desc* desc, const void* c, const void* b, const void* h,
+                          const void* u0, const void* w, const void* gy, int32_t iters, void* stream,
+                          smnn_tune_result* best, smnn_tune_result* all, int32_t cap, int32_t* n_all) {
+  if (!desc || !c || !b || !h || !w || !gy || !best || iters < 1 || cap < 0) return SMNN_ERR_INVALID_ARG;
+  if (desc->n_init > 0 && !u0) return SMNN_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int K = desc->order + 1;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return SMNN_ERR_HIP;
+  int n = 0;
+  smnn_tune_result cur{};
+  cur.ms = -1.f;
+  auto visit = [&](smnn_plan_desc d) -> smnn_status {
+    if (!supported(K, d.chunk) || !supported(K, d.chunk_upper)) return SMNN_OK;
+    float ms = 0.f;
+    const smnn_status s = time_candidate(d, c, b, h, u0, w, gy, iters, st, &ms);
+    if (s == SMNN_ERR_UNSUPPORTED) return SMNN_OK;
+    if (s != SMNN_OK) return s;
+    smnn_tune_result r{d.chunk, d.chunk_upper, d.block, d.max_blocks, ms};
+    if (all && n < cap) all[n] = r;
+    ++n;
+    if (cur.ms < 0.f || ms < cur.ms) cur = r;
+    return SMNN_OK;
+  };
+  smnn_plan_desc d = *desc;
+  d.block = d.block ? d.block : 256;
+  const int chunks[] = {4, 8, 16};
+  // 1. chunk lengths (level 0 x separator levels), default launch shape
+  for (int l0 : chunks)
+    for (int l1 : chunks) {
+      d.chunk = l0;
+      d.chunk_upper = l1;
+      d.max_blocks = 0;
+      const smnn_status s = visit(d);
+      if (s != SMNN_OK) return s;
+    }
+  if (cur.ms < 0.f) return SMNN_ERR_UNSUPPORTED;
+  // 2. workgroup size and persistent grid for the best chunk lengths
+  d.chunk = cur.chunk;
+  d.chunk_upper = cur.chunk_upper;
+  const int blocks[] = {64, 128, 256};
+  const int grids[] = {0, 2, 4, 8};
+  for (int bl : blocks)
+    for (int g : grids) {
+      if (bl == cur.block && g == 0) continue;
+      d.block = bl;
+      d.max_blocks = g ? g * cus * (256 / bl) : 0;
+      const smnn_status s = visit(d);
+      if (s != SMNN_OK) return s;
+    }
+  *best = cur;
+  if (n_all) *n_all = n;
+  return SMNN_OK;
+}
+
 const char* smnn_status_string(smnn_status s) {
   switch (s) {
     case SMNN_OK: return "ok";

@@ -310,28 +310,35 @@ SMNN_HD void pair_residual(const double (&pw)[Dim<K>::P], double ws, const doubl
 #pragma clang fp contract(off)
 #endif
   constexpr Coef<K> C{};
+  double wp[K];
 #pragma unroll
-  for (int j = 0; j < K; ++j) { cl[j] = 0.0; cr[j] = 0.0; }
+  for (int j = 0; j < K; ++j) {
+    wp[j] = ws * pw[j];
+    cl[j] = 0.0;
+    cr[j] = 0.0;
+  }
 #pragma unroll
   for (int r = 0; r < K; ++r) {
-    // forward row r: sum_{j>=r} w_s s^j/(j-r)! v_{t,j} - w_s s^r v_{t+1,r}
-    double af = -ws * pw[r] * vn[r];
+    // weighted coefficients of forward row r on v_{t,j} (and, with sign
+    // (-1)^{j-r}, of backward row r on v_{t+1,j}): w_s s^j/(j-r)!
+    double cf[K];
 #pragma unroll
-    for (int j = r; j < K; ++j) af += ws * pw[j] * C.inv_fact[j - r] * vt[j];
-    const double rf = -af;
-    // backward row r: sum_{j>=r} w_s (-1)^{j-r} s^j/(j-r)! v_{t+1,j} - w_s s^r v_{t,r}
-    double ab = -ws * pw[r] * vt[r];
+    for (int j = r; j < K; ++j) cf[j] = (j == r) ? wp[j] : wp[j] * C.inv_fact[j - r];
+    // forward row r: sum_{j>=r} cf_j v_{t,j} - w_s s^r v_{t+1,r};  rho = -(row . v)
+    double af = -(wp[r] * vn[r]);
 #pragma unroll
-    for (int j = r; j < K; ++j)
-      ab += ws * pw[j] * (((j - r) & 1) ? -C.inv_fact[j - r] : C.inv_fact[j - r]) * vn[j];
-    const double rb = -ab;
+    for (int j = r; j < K; ++j) af = fma(cf[j], vt[j], af);
+    // backward row r: sum_{j>=r} (-1)^{j-r} cf_j v_{t+1,j} - w_s s^r v_{t,r}
+    double ab = -(wp[r] * vt[r]);
+#pragma unroll
+    for (int j = r; j < K; ++j) ab = fma(((j - r) & 1) ? -cf[j] : cf[j], vn[j], ab);
 #pragma unroll
     for (int j = r; j < K; ++j) {
-      cl[j] += ws * pw[j] * C.inv_fact[j - r] * rf;
-      cr[j] += ws * pw[j] * (((j - r) & 1) ? -C.inv_fact[j - r] : C.inv_fact[j - r]) * rb;
+      cl[j] = fma(cf[j], -af, cl[j]);
+      cr[j] = fma(((j - r) & 1) ? -cf[j] : cf[j], -ab, cr[j]);
     }
-    cr[r] += -ws * pw[r] * rf;
-    cl[r] += -ws * pw[r] * rb;
+    cr[r] = fma(wp[r], af, cr[r]);     // (-w_s s^r) * rho_f, rho_f = -af
+    cl[r] = fma(wp[r], ab, cl[r]);     // (-w_s s^r) * rho_b
   }
 }
 
@@ -577,6 +584,10 @@ struct Src0 {
   const TIO* v;      // [n][K]  previous iterate (RHS_RESID, RHS_GRESID)
   int64_t n;
   Inst<K> p;
+  // residual modes: contribution of pair (next_node-1, next_node) to next_node,
+  // computed with the previous node (nodes are visited in increasing order)
+  mutable double carry[K];
+  mutable int64_t carry_node = -1;
 
   SMNN_HD double ld(const TIO* ptr, int64_t idx) const { return static_cast<double>(ptr[idx]); }
 
@@ -599,29 +610,37 @@ struct Src0 {
     for (int r = 0; r < K; ++r) vi[r] = ld(v, i * K + r);
     double e = (RHS == RHS_RESID) ? ld(d, i) : 0.0;
 #pragma unroll
-    for (int r = 0; r < K; ++r) e -= ci[r] * vi[r];
+    for (int r = 0; r < K; ++r) e = fma(-ci[r], vi[r], e);
+    const double we = wg2 * e;
 #pragma unroll
-    for (int r = 0; r < K; ++r) f[r] = (RHS == RHS_GRESID ? ld(g, i * K + r) : 0.0) + wg2 * ci[r] * e;
+    for (int r = 0; r < K; ++r) f[r] = (RHS == RHS_GRESID) ? fma(ci[r], we, ld(g, i * K + r)) : ci[r] * we;
     if (i == 0) {
 #pragma unroll
       for (int r = 0; r < K; ++r)
         if (r < p.n_init) f[r] += wi2 * ((RHS == RHS_RESID ? p.u0[r] : 0.0) - vi[r]);
     }
-    if (has_next) {
-      double vn[K], cl[K], cr[K];
-#pragma unroll
-      for (int r = 0; r < K; ++r) vn[r] = ld(v, (i + 1) * K + r);
-      pair_residual<K>(pr, p.ws, vi, vn, cl, cr);
-#pragma unroll
-      for (int r = 0; r < K; ++r) f[r] += cl[r];
-    }
     if (has_prev) {
-      double vp[K], cl[K], cr[K];
+      double cr[K];
+      if (carry_node == i) {
 #pragma unroll
-      for (int r = 0; r < K; ++r) vp[r] = ld(v, (i - 1) * K + r);
-      pair_residual<K>(pl, p.ws, vp, vi, cl, cr);
+        for (int r = 0; r < K; ++r) cr[r] = carry[r];
+      } else {
+        double vp[K], cl[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r) vp[r] = ld(v, (i - 1) * K + r);
+        pair_residual<K>(pl, p.ws, vp, vi, cl, cr);
+      }
 #pragma unroll
       for (int r = 0; r < K; ++r) f[r] += cr[r];
+    }
+    if (has_next) {
+      double vn[K], cl[K];
+#pragma unroll
+      for (int r = 0; r < K; ++r) vn[r] = ld(v, (i + 1) * K + r);
+      pair_residual<K>(pr, p.ws, vi, vn, cl, carry);
+      carry_node = i + 1;
+#pragma unroll
+      for (int r = 0; r < K; ++r) f[r] += cl[r];
     }
   }
 

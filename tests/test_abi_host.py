@@ -27,7 +27,8 @@ def _declared():
 def test_header_declares_the_boundary():
     names = _declared()
     for required in ("smnn_plan_create", "smnn_plan_destroy", "smnn_plan_sizes", "smnn_forward",
-                     "smnn_backward", "smnn_status_string", "smnn_plan_query"):
+                     "smnn_backward", "smnn_status_string", "smnn_plan_query", "smnn_autotune",
+                     "smnn_trace_enable", "smnn_trace_read"):
         assert required in names
 
 
@@ -84,6 +85,9 @@ def test_null_arguments_rejected():
     assert lib.smnn_forward(*fwd) == 1
     bwd = [None] * 8 + [0] + [None] * 7 + [0, None, None]
     assert lib.smnn_backward(*bwd) == 1
+    assert lib.smnn_autotune(None, None, None, None, None, None, None, 1, None, None, None, 0, None) == 1
+    assert lib.smnn_trace_enable(None, 4) == 1
+    assert lib.smnn_trace_read(None, None, 0) == -1
 
 
 def test_levels_geometry_matches_partition_rule():
