@@ -498,12 +498,20 @@ SMNN_HD void reduce_chunk(const Src& src, int64_t a, int64_t b, bool has_left, b
   }
 }
 
+// Receives nothing: the caller reads x afterwards.
+struct NoSink {
+  template <int K>
+  SMNN_HD void node(int64_t, const double (&)[K]) {}
+};
+
 // Solve the chunk interior a..b with the separator values xl (node a-1) and
 // xr (node b+1) known.  x[u] receives node a+u for u = 0..b-a (it first holds
-// the forward-substituted right-hand sides, then the solution).
-template <int K, int L, class Src>
+// the forward-substituted right-hand sides, then the solution); sink.node(i,
+// x_i) is called as each node is finished, in decreasing order of i.
+template <int K, int L, class Src, class Sink = NoSink>
 SMNN_HD int backsub_chunk(const Src& src, int64_t a, int64_t b, bool has_left, bool has_right,
-                          const double (&xl)[K], const double (&xr)[K], double (&x)[L][K]) {
+                          const double (&xl)[K], const double (&xr)[K], double (&x)[L][K],
+                          Sink&& sink = Sink()) {
   constexpr int Q = Dim<K>::Q, KK = Dim<K>::KK;
   double Ls[L][Q];
   int fail = 0;
@@ -553,6 +561,7 @@ SMNN_HD int backsub_chunk(const Src& src, int64_t a, int64_t b, bool has_left, b
       for (int e = 0; e < K; ++e) x[u][e] += t[e];
     }
     usolve<K>(Ls[u], x[u]);                    // x_i = L^{-T}(ghat_i - L^{-1} B_i^T x_{i+1})
+    sink.template node<K>(i, x[u]);
   }
   return fail;
 }
@@ -687,61 +696,99 @@ struct Src0 {
   }
 };
 
-// Parameter gradients of the rows owned by one chunk (level 0).  lam and y
-// hold nodes a-1 .. last (index 0 = node a-1) with last = b+1 when the chunk
-// has a right separator, else b.  Per weighted row a~ . y = b~ with
-// rho = a~.y - b~ and mu = a~.lam, dl/dtheta = -[(da~.lam) rho + mu (da~.y - db~)]
-// (Eq. 14 chained through the row).  The chunk owns the governing rows of its
-// nodes a..last, the initial rows when a = 0, and the smoothness pairs
-// (t, t+1) for t = a-1 .. last-1.  dw receives this chunk's partial sums.
-template <int K, int L, class TIO>
-SMNN_HD void grad_chunk(const TIO* c, const TIO* d, const TIO* s, int64_t n, const Inst<K>& p,
-                        const ChunkGeom& G, const double (&lam)[L + 1][K], const double (&y)[L + 1][K],
-                        TIO* dc, TIO* dd, TIO* ds, TIO* du0, double (&dw)[3]) {
-  const int64_t a = G.a;
-  const int64_t last = G.has_right ? G.b + 1 : G.b;
-  const double wg2 = p.wg * p.wg, wi2 = p.wi * p.wi;
-  double dwg = 0.0, dwi = 0.0, dws = 0.0;
+// Level-0 solution sink: out_i = (v_i +) x_i in the I/O type.
+template <class TIO, bool ADD>
+struct StoreSink {
+  TIO* out;        // this instance's [n][K]
+  const TIO* v;    // previous iterate (ADD)
+  template <int K>
+  SMNN_HD void node(int64_t i, const double (&x)[K]) {
 #pragma unroll
-  for (int u = 0; u < L; ++u) {
-    const int64_t t = a + u;
-    if (t > last) break;
-    double e = -static_cast<double>(d[t]), f = 0.0;
+    for (int e = 0; e < K; ++e) {
+      double val = x[e];
+      if (ADD) val += static_cast<double>(v[i * K + e]);
+      out[i * K + e] = static_cast<TIO>(val);
+    }
+  }
+};
+
+// Level-0 gradient sink.  As the back-substitution finishes node i (in
+// decreasing order) with lam_i = (v_i +) x_i it forms the gradients of the
+// rows the chunk owns: the governing row of node i, the initial rows when
+// i = 0, and the smoothness pair (i, i+1), using the node finished just
+// before.  Per weighted row a~.y = b~ with rho = a~.y - b~ and mu = a~.lam,
+// dl/dtheta = -[(da~.lam) rho + mu (da~.y - db~)] (Eq. 14 chained through the
+// row).  dw accumulates this chunk's partial sums.
+template <int K, class TIO, bool ADD>
+struct GradSink {
+  const TIO *c, *d, *s, *y, *v;
+  TIO *dc, *dd, *ds, *du0;
+  Inst<K> p;
+  double lam_n[K], y_n[K];   // node i+1 (the one finished before)
+  bool have_next = false;
+  double dw[3] = {0.0, 0.0, 0.0};
+
+  SMNN_HD void lam_y(int64_t i, const double (&x)[K], double (&lam)[K], double (&yi)[K]) const {
+#pragma unroll
+    for (int e = 0; e < K; ++e) {
+      lam[e] = x[e] + (ADD ? static_cast<double>(v[i * K + e]) : 0.0);
+      yi[e] = static_cast<double>(y[i * K + e]);
+    }
+  }
+  SMNN_HD void governing(int64_t i, const double (&lam)[K], const double (&yi)[K]) {
+    const double wg2 = p.wg * p.wg;
+    double e = -static_cast<double>(d[i]), f = 0.0;
 #pragma unroll
     for (int r = 0; r < K; ++r) {
-      const double cr = static_cast<double>(c[t * K + r]);
-      e += cr * y[u + 1][r];
-      f += cr * lam[u + 1][r];
+      const double cr = static_cast<double>(c[i * K + r]);
+      e = fma(cr, yi[r], e);
+      f = fma(cr, lam[r], f);
     }
 #pragma unroll
-    for (int r = 0; r < K; ++r) dc[t * K + r] = static_cast<TIO>(-wg2 * (e * lam[u + 1][r] + f * y[u + 1][r]));
-    dd[t] = static_cast<TIO>(wg2 * f);
-    dwg += -2.0 * p.wg * e * f;
-  }
-  if (a == 0) {
+    for (int r = 0; r < K; ++r) dc[i * K + r] = static_cast<TIO>(-wg2 * (e * lam[r] + f * yi[r]));
+    dd[i] = static_cast<TIO>(wg2 * f);
+    dw[0] += -2.0 * p.wg * e * f;
+    if (i == 0) {
 #pragma unroll
-    for (int r = 0; r < K; ++r)
-      if (r < p.n_init) {
-        du0[r] = static_cast<TIO>(wi2 * lam[1][r]);
-        dwi += -2.0 * p.wi * (y[1][r] - p.u0[r]) * lam[1][r];
-      }
+      for (int r = 0; r < K; ++r)
+        if (r < p.n_init) {
+          du0[r] = static_cast<TIO>(p.wi * p.wi * lam[r]);
+          dw[1] += -2.0 * p.wi * (yi[r] - p.u0[r]) * lam[r];
+        }
+    }
   }
+  SMNN_HD void pair(int64_t i, const double (&lam)[K], const double (&yi)[K]) {
+    double g_s = 0.0, g_w = 0.0;
+    pair_grad<K>(static_cast<double>(s[i]), p.ws, yi, y_n, lam, lam_n, g_s, g_w);
+    ds[i] = static_cast<TIO>(g_s);
+    dw[2] += g_w;
+  }
+  // the chunk's right separator (owned; finished by the level above)
+  SMNN_HD void start(int64_t i, const double (&x)[K]) {
+    double lam[K], yi[K];
+    lam_y(i, x, lam, yi);
+    governing(i, lam, yi);
 #pragma unroll
-  for (int u = -1; u < L; ++u) {
-    const int64_t t = a + u;
-    if (t < 0) continue;
-    if (t + 1 > last) break;
-    double gs = 0.0, gw = 0.0;
-    pair_grad<K>(static_cast<double>(s[t]), p.ws, y[u + 1], y[u + 2 <= L ? u + 2 : L], lam[u + 1],
-                 lam[u + 2 <= L ? u + 2 : L], gs, gw);
-    ds[t] = static_cast<TIO>(gs);
-    dws += gw;
+    for (int e = 0; e < K; ++e) { lam_n[e] = lam[e]; y_n[e] = yi[e]; }
+    have_next = true;
   }
-  if (!G.has_right) ds[n - 1] = static_cast<TIO>(0.0);
-  dw[0] = dwg;
-  dw[1] = dwi;
-  dw[2] = dws;
-}
+  template <int KK>
+  SMNN_HD void node(int64_t i, const double (&x)[KK]) {
+    double lam[K], yi[K];
+    lam_y(i, x, lam, yi);
+    governing(i, lam, yi);
+    if (have_next) pair(i, lam, yi);
+#pragma unroll
+    for (int e = 0; e < K; ++e) { lam_n[e] = lam[e]; y_n[e] = yi[e]; }
+    have_next = true;
+  }
+  // the chunk's left separator: only the smoothness pair (i, i+1) is owned here
+  SMNN_HD void left(int64_t i, const double (&x)[K]) {
+    double lam[K], yi[K];
+    lam_y(i, x, lam, yi);
+    pair(i, lam, yi);
+  }
+};
 
 // Node data of a reduced (separator) level: records written by the level
 // below.  rec[node] = {A packed (Q), B = block (node+1, node) (K*K)}.

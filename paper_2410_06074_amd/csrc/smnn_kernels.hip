@@ -237,49 +237,30 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub0(LevelDev l0, L
       xr[e] = geo.has_right ? l1.x[(up + j) * K + e] : 0.0;
     }
     const auto S = make_src0<K, TIO, RHS>(a, inst, off, n);
-    const int fail = backsub_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs);
-    if (fail) report_fail(a, inst, 0, geo.a + fail - 1);
-    const int64_t last = geo.has_right ? geo.b + 1 : geo.b;
     const TIO* v = ADD ? static_cast<const TIO*>(a.v) + off * K : nullptr;
+    int fail;
     if (OUT == OUT_STORE) {
-      TIO* out = static_cast<TIO*>(a.out) + off * K;
-#pragma unroll
-      for (int u = 0; u < L; ++u) {
-        const int64_t t = geo.a + u;
-        if (t > last) break;
-#pragma unroll
-        for (int e = 0; e < K; ++e) {
-          double val = (t <= geo.b) ? xs[u][e] : xr[e];
-          if (ADD) val += static_cast<double>(v[t * K + e]);
-          out[t * K + e] = static_cast<TIO>(val);
-        }
-      }
+      StoreSink<TIO, ADD> sink{static_cast<TIO*>(a.out) + off * K, v};
+      if (geo.has_right) sink.template node<K>(geo.b + 1, xr);   // owned right separator
+      fail = backsub_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
     } else {
-      // lam and y at nodes a-1 .. last (index 0 = node a-1)
-      double lam[L + 1][K], yv[L + 1][K];
-      const TIO* y = static_cast<const TIO*>(a.y) + off * K;
+      GradSink<K, TIO, ADD> sink;
+      sink.c = S.c; sink.d = S.d; sink.s = S.s;
+      sink.y = static_cast<const TIO*>(a.y) + off * K;
+      sink.v = v;
+      sink.dc = static_cast<TIO*>(a.dc) + off * K;
+      sink.dd = static_cast<TIO*>(a.dd) + off;
+      sink.ds = static_cast<TIO*>(a.ds) + off;
+      sink.du0 = static_cast<TIO*>(a.du0) + inst * a.n_init;
+      sink.p = S.p;
+      if (geo.has_right) sink.start(geo.b + 1, xr);
+      fail = backsub_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
+      if (geo.has_left) sink.left(geo.a - 1, xl);
+      if (!geo.has_right) sink.ds[n - 1] = static_cast<TIO>(0.0);   // s of the last point is unused
 #pragma unroll
-      for (int u = -1; u < L; ++u) {
-        const int64_t t = geo.a + u;
-        const bool in = (t >= 0) && (t <= last);
-#pragma unroll
-        for (int e = 0; e < K; ++e) {
-          double xv = 0.0;
-          if (u == -1) xv = xl[e];
-          else if (t <= geo.b) xv = xs[u >= 0 ? u : 0][e];
-          else xv = xr[e];
-          if (ADD && in) xv += static_cast<double>(v[t * K + e]);
-          lam[u + 1][e] = in ? xv : 0.0;
-          yv[u + 1][e] = in ? static_cast<double>(y[t * K + e]) : 0.0;
-        }
-      }
-      double dwp[3];
-      grad_chunk<K, L, TIO>(S.c, S.d, S.s, n, S.p, geo, lam, yv, static_cast<TIO*>(a.dc) + off * K,
-                            static_cast<TIO*>(a.dd) + off, static_cast<TIO*>(a.ds) + off,
-                            static_cast<TIO*>(a.du0) + inst * a.n_init, dwp);
-#pragma unroll
-      for (int e = 0; e < 3; ++e) a.dw_part[g * 3 + e] = dwp[e];
+      for (int e = 0; e < 3; ++e) a.dw_part[g * 3 + e] = sink.dw[e];
     }
+    if (fail) report_fail(a, inst, 0, geo.a + fail - 1);
   }
 }
 

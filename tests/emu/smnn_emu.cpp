@@ -96,6 +96,7 @@ struct Emu {
   // level-0 back-substitution: out = (v ? v : 0) + x  for every owned node
   template <int RHS>
   void backsub0(const TIO* g, const TIO* v, TIO* out, std::vector<double>* full) {
+    constexpr bool ADD = (RHS == RHS_RESID || RHS == RHS_GRESID);
     const Level& lvl = lv[0];
     for (int64_t ch = 0; ch < lvl.chunks; ++ch) {
       const int64_t i = lvl.chunk_inst[ch];
@@ -105,16 +106,21 @@ struct Emu {
       const int64_t up = lv.size() > 1 ? lv[1].node_off[i] : 0;
       if (G.has_left) for (int e = 0; e < K; ++e) xl[e] = x[1][(up + j - 1) * K + e];
       if (G.has_right) for (int e = 0; e < K; ++e) xr[e] = x[1][(up + j) * K + e];
-      backsub_chunk<K, L0>(src0<RHS>(i, g, v), G.a, G.b, G.has_left, G.has_right, xl, xr, xs);
       const int64_t o = lvl.node_off[i];
-      const int64_t last = G.has_right ? G.b + 1 : G.b;
-      for (int64_t t = G.a; t <= last; ++t)
-        for (int e = 0; e < K; ++e) {
-          const double xv = (t <= G.b) ? xs[t - G.a][e] : xr[e];
-          const double val = (v ? (double)v[(o + t) * K + e] : 0.0) + xv;
-          if (out) out[(o + t) * K + e] = (TIO)val;
-          if (full) (*full)[(o + t) * K + e] = val;
-        }
+      std::vector<TIO> tmp;
+      TIO* dst = out;
+      if (!dst) { tmp.assign(lvl.n[i] * K, TIO(0)); }
+      StoreSink<TIO, ADD> sink{dst ? dst + o * K : tmp.data(), v ? v + o * K : nullptr};
+      if (G.has_right) sink.template node<K>(G.b + 1, xr);
+      backsub_chunk<K, L0>(src0<RHS>(i, g, v), G.a, G.b, G.has_left, G.has_right, xl, xr, xs, sink);
+      if (full) {
+        const int64_t last = G.has_right ? G.b + 1 : G.b;
+        for (int64_t t = G.a; t <= last; ++t)
+          for (int e = 0; e < K; ++e) {
+            const double xv = (t <= G.b) ? xs[t - G.a][e] : xr[e];
+            (*full)[(o + t) * K + e] = (v ? (double)v[(o + t) * K + e] : 0.0) + xv;
+          }
+      }
     }
   }
 
@@ -134,26 +140,18 @@ struct Emu {
       if (G.has_left) for (int e = 0; e < K; ++e) xl[e] = x[1][(up + j - 1) * K + e];
       if (G.has_right) for (int e = 0; e < K; ++e) xr[e] = x[1][(up + j) * K + e];
       const auto S = src0<RHS>(i, g, v);
-      backsub_chunk<K, L0>(S, G.a, G.b, G.has_left, G.has_right, xl, xr, xs);
       const int64_t o = lvl.node_off[i];
-      const int64_t last = G.has_right ? G.b + 1 : G.b;
-      double lam[L0 + 1][K], yv[L0 + 1][K];
-      for (int u = -1; u < L0; ++u) {
-        const int64_t t = G.a + u;
-        const bool in = t >= 0 && t <= last;
-        for (int e = 0; e < K; ++e) {
-          double xv = 0.0;
-          if (u == -1) xv = xl[e];
-          else if (t <= G.b) xv = xs[u][e];
-          else xv = xr[e];
-          if (ADD && in) xv += (double)v[(o + t) * K + e];
-          lam[u + 1][e] = in ? xv : 0.0;
-          yv[u + 1][e] = in ? (double)y[(o + t) * K + e] : 0.0;
-        }
-      }
-      double dwp[3];
-      grad_chunk<K, L0, TIO>(S.c, S.d, S.s, S.n, S.p, G, lam, yv, dc + o * K, dd + o, ds + o, du0 + i * n_init, dwp);
-      for (int e = 0; e < 3; ++e) dw_part[ch * 3 + e] = dwp[e];
+      GradSink<K, TIO, ADD> sink;
+      sink.c = S.c; sink.d = S.d; sink.s = S.s;
+      sink.y = y + o * K;
+      sink.v = v ? v + o * K : nullptr;
+      sink.dc = dc + o * K; sink.dd = dd + o; sink.ds = ds + o; sink.du0 = du0 + i * n_init;
+      sink.p = S.p;
+      if (G.has_right) sink.start(G.b + 1, xr);
+      backsub_chunk<K, L0>(S, G.a, G.b, G.has_left, G.has_right, xl, xr, xs, sink);
+      if (G.has_left) sink.left(G.a - 1, xl);
+      if (!G.has_right) sink.ds[lvl.n[i] - 1] = (TIO)0;
+      for (int e = 0; e < 3; ++e) dw_part[ch * 3 + e] = sink.dw[e];
     }
   }
 
