@@ -88,7 +88,7 @@ def describe(name, bt, mode):
 
 
 # --------------------------------------------------------------- GPU run
-def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0, graph=True, tune=False):
+def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0, graph=True, tune=False, block=0):
     import numpy as np
     import torch
     from paper_2410_06074_amd import Plan
@@ -102,7 +102,7 @@ def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0, graph=
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt)
     c, b, h, u0, w = t(bt.c), t(bt.b), t(bt.h), t(bt.u0), t(bt.w)
     tuned = None
-    block = max_blocks = 0
+    max_blocks = 0
     if tune:
         from paper_2410_06074_amd import autotune
         gy0 = torch.ones_like(c)
@@ -233,6 +233,7 @@ def main():
     ap.add_argument("--chunk-upper", type=int, default=0, help="nodes per lane at levels >= 1 (0: default)")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of hipGraph replays")
     ap.add_argument("--autotune", action="store_true", help="pick the launch mapping with smnn_autotune first")
+    ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: library default)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solve is per-instance independent and this build has no "
@@ -253,7 +254,8 @@ def main():
     for m in modes:
         log("mode", m)
         results[m] = run_mode(bt, m, args.steps, args.warmup, sample, chunk=args.chunk,
-                              chunk_upper=args.chunk_upper, graph=not args.no_graph, tune=args.autotune)
+                              chunk_upper=args.chunk_upper, graph=not args.no_graph, tune=args.autotune,
+                              block=args.block)
         r = results[m]
         log("  %.3f ms/step (eager %.3f, traced %.3f), %.3e steps/s, err %.2e, chunk %s, levels %s"
             % (r["ms"], r["ms_eager"], r["ms_traced"], bt.total_steps / (r["ms"] * 1e-3), r["err"], r["chunk"],

@@ -165,6 +165,23 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   p->cfg.block = d->block ? d->block : 256;
   p->cfg.max_blocks = d->max_blocks;
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return SMNN_ERR_HIP; }
+  int lds_max = 0;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess ||
+      lds_max <= 0) {
+    delete p;
+    return SMNN_ERR_HIP;
+  }
+  p->cfg.lds_max = lds_max;
+  // every level-0 kernel variant must fit one wave's tile into LDS
+  {
+    const int combos[6][2] = {{RHS_BETA, OUT_STORE}, {RHS_RESID, OUT_STORE}, {RHS_G, OUT_STORE},
+                              {RHS_GRESID, OUT_STORE}, {RHS_G, OUT_GRAD}, {RHS_GRESID, OUT_GRAD}};
+    for (const auto& cb : combos)
+      if (level0_lds_bytes(K, L0, p->f32, cb[0], cb[1]) > static_cast<size_t>(lds_max)) {
+        delete p;
+        return SMNN_ERR_UNSUPPORTED;
+      }
+  }
 
   std::vector<Level> lv = build_levels(T, L0, L1);
   p->S = lv[0].nodes;
@@ -208,11 +225,21 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
     no[l] = mb; mb = align_up(mb + sizeof(int64_t) * (p->N + 1));
     ci[l] = mb; mb = align_up(mb + sizeof(int32_t) * std::max<int64_t>(lv[l].chunks, 1));
   }
+  const size_t cs = mb;   // level-0 chunk_step
+  mb = align_up(mb + sizeof(int64_t) * (lv[0].chunks + 1));
   std::vector<char> host(mb, 0);
   for (size_t l = 0; l < lv.size(); ++l) {
     std::copy(lv[l].chunk_off.begin(), lv[l].chunk_off.end(), reinterpret_cast<int64_t*>(host.data() + co[l]));
     std::copy(lv[l].node_off.begin(), lv[l].node_off.end(), reinterpret_cast<int64_t*>(host.data() + no[l]));
     std::copy(lv[l].chunk_inst.begin(), lv[l].chunk_inst.end(), reinterpret_cast<int32_t*>(host.data() + ci[l]));
+  }
+  {
+    int64_t* step = reinterpret_cast<int64_t*>(host.data() + cs);
+    for (int64_t g = 0; g < lv[0].chunks; ++g) {
+      const int32_t i = lv[0].chunk_inst[g];
+      step[g] = lv[0].node_off[i] + (g - lv[0].chunk_off[i]) * L0;
+    }
+    step[lv[0].chunks] = lv[0].nodes;
   }
   if (hipMalloc(&p->meta, mb) != hipSuccess) { delete p; return SMNN_ERR_HIP; }
   if (hipMemcpy(p->meta, host.data(), mb, hipMemcpyHostToDevice) != hipSuccess) {
@@ -229,6 +256,7 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
     p->lev[l].chunks = lv[l].chunks;
     p->lev[l].nodes = lv[l].nodes;
   }
+  p->lev[0].chunk_step = reinterpret_cast<const int64_t*>(m + cs);
   *out = p;
   return SMNN_OK;
 }

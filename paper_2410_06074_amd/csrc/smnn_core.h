@@ -586,19 +586,21 @@ enum RhsMode : int {
 // TIO is the element type of the arrays in memory (double or float).
 template <int K, class TIO, int RHS>
 struct Src0 {
-  const TIO* c;      // [n][K] of this instance
-  const TIO* d;      // [n]
-  const TIO* s;      // [n]  (s[n-1] unused)
-  const TIO* g;      // [n][K]  dl/dy (RHS_G, RHS_GRESID)
-  const TIO* v;      // [n][K]  previous iterate (RHS_RESID, RHS_GRESID)
+  const TIO* c;      // [..][K] node i of this instance is row o + i
+  const TIO* d;      // [..]
+  const TIO* s;      // [..]  (s of the last node unused)
+  const TIO* g;      // [..][K]  dl/dy (RHS_G, RHS_GRESID)
+  const TIO* v;      // [..][K]  previous iterate (RHS_RESID, RHS_GRESID)
   int64_t n;
+  int64_t o = 0;     // row of node 0 in the arrays above
   Inst<K> p;
   // residual modes: contribution of pair (next_node-1, next_node) to next_node,
   // computed with the previous node (nodes are visited in increasing order)
   mutable double carry[K];
   mutable int64_t carry_node = -1;
 
-  SMNN_HD double ld(const TIO* ptr, int64_t idx) const { return static_cast<double>(ptr[idx]); }
+  SMNN_HD double ld(const TIO* ptr, int64_t i) const { return static_cast<double>(ptr[o + i]); }
+  SMNN_HD double ldk(const TIO* ptr, int64_t i, int r) const { return static_cast<double>(ptr[(o + i) * K + r]); }
 
   SMNN_HD void coupling(int64_t i, double (&B)[Dim<K>::KK]) const {
     double pw[Dim<K>::P];
@@ -616,13 +618,13 @@ struct Src0 {
     const double wg2 = p.wg * p.wg, wi2 = p.wi * p.wi;
     double vi[K];
 #pragma unroll
-    for (int r = 0; r < K; ++r) vi[r] = ld(v, i * K + r);
+    for (int r = 0; r < K; ++r) vi[r] = ldk(v, i, r);
     double e = (RHS == RHS_RESID) ? ld(d, i) : 0.0;
 #pragma unroll
     for (int r = 0; r < K; ++r) e = fma(-ci[r], vi[r], e);
     const double we = wg2 * e;
 #pragma unroll
-    for (int r = 0; r < K; ++r) f[r] = (RHS == RHS_GRESID) ? fma(ci[r], we, ld(g, i * K + r)) : ci[r] * we;
+    for (int r = 0; r < K; ++r) f[r] = (RHS == RHS_GRESID) ? fma(ci[r], we, ldk(g, i, r)) : ci[r] * we;
     if (i == 0) {
 #pragma unroll
       for (int r = 0; r < K; ++r)
@@ -636,7 +638,7 @@ struct Src0 {
       } else {
         double vp[K], cl[K];
 #pragma unroll
-        for (int r = 0; r < K; ++r) vp[r] = ld(v, (i - 1) * K + r);
+        for (int r = 0; r < K; ++r) vp[r] = ldk(v, i - 1, r);
         pair_residual<K>(pl, p.ws, vp, vi, cl, cr);
       }
 #pragma unroll
@@ -645,7 +647,7 @@ struct Src0 {
     if (has_next) {
       double vn[K], cl[K];
 #pragma unroll
-      for (int r = 0; r < K; ++r) vn[r] = ld(v, (i + 1) * K + r);
+      for (int r = 0; r < K; ++r) vn[r] = ldk(v, i + 1, r);
       pair_residual<K>(pr, p.ws, vi, vn, cl, carry);
       carry_node = i + 1;
 #pragma unroll
@@ -656,7 +658,7 @@ struct Src0 {
   SMNN_HD void load(int64_t i, double (&A)[Dim<K>::Q], double (&f)[K], double (&Bp)[Dim<K>::KK]) const {
     double ci[K];
 #pragma unroll
-    for (int r = 0; r < K; ++r) ci[r] = ld(c, i * K + r);
+    for (int r = 0; r < K; ++r) ci[r] = ldk(c, i, r);
     const double wg2 = p.wg * p.wg, wi2 = p.wi * p.wi, ws2 = p.ws * p.ws;
 #pragma unroll
     for (int r = 0; r < K; ++r)
@@ -689,7 +691,7 @@ struct Src0 {
       }
     } else if (RHS == RHS_G) {
 #pragma unroll
-      for (int r = 0; r < K; ++r) f[r] = ld(g, i * K + r);
+      for (int r = 0; r < K; ++r) f[r] = ldk(g, i, r);
     } else {
       residual_rhs(i, ci, has_next, has_prev, pl, pr, f);
     }
@@ -700,13 +702,14 @@ struct Src0 {
 template <class TIO, bool ADD>
 struct StoreSink {
   TIO* out;        // this instance's [n][K]
-  const TIO* v;    // previous iterate (ADD)
+  const TIO* v;    // previous iterate (ADD): node i is row vo + i
+  int64_t vo = 0;
   template <int K>
   SMNN_HD void node(int64_t i, const double (&x)[K]) {
 #pragma unroll
     for (int e = 0; e < K; ++e) {
       double val = x[e];
-      if (ADD) val += static_cast<double>(v[i * K + e]);
+      if (ADD) val += static_cast<double>(v[(vo + i) * K + e]);
       out[i * K + e] = static_cast<TIO>(val);
     }
   }
@@ -721,8 +724,9 @@ struct StoreSink {
 // row).  dw accumulates this chunk's partial sums.
 template <int K, class TIO, bool ADD>
 struct GradSink {
-  const TIO *c, *d, *s, *y, *v;
-  TIO *dc, *dd, *ds, *du0;
+  const TIO *c, *d, *s, *y, *v;   // inputs: node i is row o + i
+  TIO *dc, *dd, *ds, *du0;        // outputs of this instance: node i is row i
+  int64_t o = 0;
   Inst<K> p;
   double lam_n[K], y_n[K];   // node i+1 (the one finished before)
   bool have_next = false;
@@ -731,16 +735,16 @@ struct GradSink {
   SMNN_HD void lam_y(int64_t i, const double (&x)[K], double (&lam)[K], double (&yi)[K]) const {
 #pragma unroll
     for (int e = 0; e < K; ++e) {
-      lam[e] = x[e] + (ADD ? static_cast<double>(v[i * K + e]) : 0.0);
-      yi[e] = static_cast<double>(y[i * K + e]);
+      lam[e] = x[e] + (ADD ? static_cast<double>(v[(o + i) * K + e]) : 0.0);
+      yi[e] = static_cast<double>(y[(o + i) * K + e]);
     }
   }
   SMNN_HD void governing(int64_t i, const double (&lam)[K], const double (&yi)[K]) {
     const double wg2 = p.wg * p.wg;
-    double e = -static_cast<double>(d[i]), f = 0.0;
+    double e = -static_cast<double>(d[o + i]), f = 0.0;
 #pragma unroll
     for (int r = 0; r < K; ++r) {
-      const double cr = static_cast<double>(c[i * K + r]);
+      const double cr = static_cast<double>(c[(o + i) * K + r]);
       e = fma(cr, yi[r], e);
       f = fma(cr, lam[r], f);
     }
@@ -759,7 +763,7 @@ struct GradSink {
   }
   SMNN_HD void pair(int64_t i, const double (&lam)[K], const double (&yi)[K]) {
     double g_s = 0.0, g_w = 0.0;
-    pair_grad<K>(static_cast<double>(s[i]), p.ws, yi, y_n, lam, lam_n, g_s, g_w);
+    pair_grad<K>(static_cast<double>(s[o + i]), p.ws, yi, y_n, lam, lam_n, g_s, g_w);
     ds[i] = static_cast<TIO>(g_s);
     dw[2] += g_w;
   }

@@ -12,6 +12,7 @@ struct LevelDev {
   const int32_t* chunk_inst = nullptr;  // [chunks]
   const int64_t* chunk_off = nullptr;   // [N+1]
   const int64_t* node_off = nullptr;    // [N+1]
+  const int64_t* chunk_step = nullptr;  // level 0: [chunks+1] global row of each chunk's first node
   int64_t chunks = 0, nodes = 0;
   double* rec = nullptr;                // level >= 1: [nodes][Q+KK] (in the factor buffer)
   double* rhs = nullptr;                // level >= 1: [nodes][K]    (workspace)
@@ -40,11 +41,14 @@ struct Level0Args {
   int n_init = 0;
   int L0 = 8, L1 = 8;        // chunk lengths of level 0 and of levels >= 1
   int64_t N = 0;
+  int wpb = 1;               // waves per workgroup of the launch (set by the launcher)
+  int64_t nwaves = 0;        // waves in the grid of the launch (set by the launcher)
 };
 
 struct Launch {
   int block = 256;      // threads per workgroup (multiple of 64)
   int max_blocks = 0;   // 0: one wave per tile; >0: persistent grid-stride cap
+  int lds_max = 65536;  // LDS bytes a workgroup may allocate on the device
 };
 
 enum OutMode : int { OUT_STORE = 0, OUT_GRAD = 1 };
@@ -61,6 +65,10 @@ hipError_t launch_backsub0(int K, int L, bool f32, int rhs_mode, int out_mode, c
                            const LevelDev* l1, const Level0Args& a, const Launch& cfg, hipStream_t st);
 hipError_t launch_dw_reduce(bool f32, const LevelDev& l0, const Level0Args& a, hipStream_t st);
 hipError_t launch_info_init(const Level0Args& a, hipStream_t st);
+
+// LDS bytes one wave of a level-0 kernel stages its tile in (0 if (K, L) is
+// not compiled in).  The largest variant of a mode is the gradient pass.
+size_t level0_lds_bytes(int K, int L, bool f32, int rhs_mode, int out_mode);
 hipError_t launch_info_finalize(const Level0Args& a, int32_t* info, hipStream_t st);
 
 bool supported(int K, int L);

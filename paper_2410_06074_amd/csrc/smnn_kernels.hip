@@ -21,6 +21,14 @@
 // memory.  Reduce tiles hold 63 new chunks per wave (lane 0 repeats the
 // previous tile's last chunk so that every separator has both of its chunks
 // in one wave); back-substitution tiles hold 64 chunks.
+//
+// Level-0 kernels first copy that range (plus one step on either side) of
+// every per-step array they read into the wave's slice of LDS, with
+// direct global-to-LDS loads that all lanes issue at once; the chunk
+// recurrences then read LDS.  A wave thus waits on HBM about once per tile
+// rather than once per node, which is what bounds the per-lane sequential
+// recurrences otherwise (a 64-lane wave holds a few hundred bytes of loads
+// in flight per node step).
 #include <hip/hip_runtime.h>
 
 #include "smnn_core.h"
@@ -41,13 +49,81 @@ constexpr int WAVE = 64;
 #define SMNN_MIN_WAVES 1
 #endif
 
-__device__ __forceinline__ int64_t wave_id() {
-  return (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / WAVE;
+// Wave index and wave count of the launch (wave-uniform values; the launch
+// shape comes in through the arguments so no dispatch-packet loads precede
+// the first memory requests).
+__device__ __forceinline__ int64_t wave_id(const Level0Args& a) {
+  const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / WAVE);
+  return static_cast<int64_t>(blockIdx.x) * a.wpb + w;
 }
-__device__ __forceinline__ int64_t wave_count() {
-  return static_cast<int64_t>(gridDim.x) * blockDim.x / WAVE;
-}
+__device__ __forceinline__ int64_t wave_count(const Level0Args& a) { return a.nwaves; }
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+// ---------------------------------------------------------- LDS staging
+// Per-step arrays a level-0 kernel variant reads (c and s always).
+template <int RHS, int OUT>
+struct Reads {
+  static constexpr bool d = RHS == RHS_BETA || RHS == RHS_RESID || OUT == OUT_GRAD;
+  static constexpr bool g = RHS == RHS_G || RHS == RHS_GRESID;
+  static constexpr bool v = RHS == RHS_RESID || RHS == RHS_GRESID;
+  static constexpr bool y = OUT == OUT_GRAD;
+};
+
+// Byte layout of one wave's LDS slice: ROWS steps of each array read, every
+// array 16-byte aligned.  A tile spans at most 64 chunks of L steps plus the
+// step before and the step after.
+template <int K, int L, class TIO, int RHS, int OUT>
+struct Stage {
+  using RD = Reads<RHS, OUT>;
+  static constexpr int ROWS = WAVE * L + 2;
+  static constexpr size_t al(size_t b) { return (b + 15) / 16 * 16; }
+  static constexpr size_t ROW_K = al(sizeof(TIO) * K * ROWS), ROW_1 = al(sizeof(TIO) * ROWS);
+  static constexpr size_t C = 0;
+  static constexpr size_t S = C + ROW_K;
+  static constexpr size_t D = S + ROW_1;
+  static constexpr size_t G = D + (RD::d ? ROW_1 : 0);
+  static constexpr size_t V = G + (RD::g ? ROW_K : 0);
+  static constexpr size_t Y = V + (RD::v ? ROW_K : 0);
+  static constexpr size_t BYTES = Y + (RD::y ? ROW_K : 0);
+};
+
+// Wave-cooperative copy of rows [lo, hi) of an array with w elements per row
+// into LDS (4 bytes per lane per load; the loads write LDS directly and are
+// all in flight together).  Every lane of the wave calls this with the same
+// arguments; the caller waits for completion before reading.
+template <class T>
+__device__ __forceinline__ void stage_rows(const void* src, int w, int64_t lo, int64_t hi, unsigned char* dst,
+                                           int lane) {
+  const int ndw = static_cast<int>((hi - lo) * w * static_cast<int64_t>(sizeof(T)) / 4);
+  const uint32_t* gsrc = reinterpret_cast<const uint32_t*>(static_cast<const T*>(src) + lo * w);
+  uint32_t* l = reinterpret_cast<uint32_t*>(dst);
+  for (int b = 0; b < ndw; b += WAVE)
+    if (b + lane < ndw) __builtin_amdgcn_global_load_lds(gsrc + b + lane, l + b, 4, 0, 0);
+}
+
+// Copies rows [lo, hi) of every array the variant reads into the slice.
+template <int K, int L, class TIO, int RHS, int OUT>
+__device__ __forceinline__ void stage_tile(const Level0Args& a, int64_t lo, int64_t hi, unsigned char* sl,
+                                           int lane) {
+  using ST = Stage<K, L, TIO, RHS, OUT>;
+  using RD = Reads<RHS, OUT>;
+  stage_rows<TIO>(a.c, K, lo, hi, sl + ST::C, lane);
+  stage_rows<TIO>(a.s, 1, lo, hi, sl + ST::S, lane);
+  if (RD::d) stage_rows<TIO>(a.d, 1, lo, hi, sl + ST::D, lane);
+  if (RD::g) stage_rows<TIO>(a.g, K, lo, hi, sl + ST::G, lane);
+  if (RD::v) stage_rows<TIO>(a.v, K, lo, hi, sl + ST::V, lane);
+  if (RD::y) stage_rows<TIO>(a.y, K, lo, hi, sl + ST::Y, lane);
+}
+
+// Rows of the tile of chunks [g0, g1): from the step before the first chunk
+// to the step after the last one, clipped to the arrays.
+__device__ __forceinline__ void tile_rows(const LevelDev& l0, int64_t g0, int64_t g1, int64_t S, int64_t& lo,
+                                          int64_t& hi) {
+  lo = l0.chunk_step[g0] - 1;
+  hi = l0.chunk_step[g1] + 1;
+  if (lo < 0) lo = 0;
+  if (hi > S) hi = S;
+}
 
 template <int K, class TIO>
 __device__ __forceinline__ Inst<K> load_inst(const Level0Args& a, int64_t i) {
@@ -58,8 +134,14 @@ __device__ __forceinline__ Inst<K> load_inst(const Level0Args& a, int64_t i) {
   p.wi = static_cast<double>(w[3 * i + 1]);
   p.ws = static_cast<double>(w[3 * i + 2]);
   p.n_init = a.n_init;
+  // unconditional loads (clamped to a valid element) so they issue together
+  const int ni = a.n_init;
+  const TIO* ub = ni > 0 ? u0 + i * ni : w + 3 * i;
 #pragma unroll
-  for (int r = 0; r < K; ++r) p.u0[r] = (r < a.n_init) ? static_cast<double>(u0[i * a.n_init + r]) : 0.0;
+  for (int r = 0; r < K; ++r) {
+    const double val = static_cast<double>(ub[ni > 0 ? (r < ni ? r : ni - 1) : 0]);
+    p.u0[r] = r < ni ? val : 0.0;
+  }
   return p;
 }
 
@@ -71,6 +153,24 @@ __device__ __forceinline__ Src0<K, TIO, RHS> make_src0(const Level0Args& a, int6
   S.s = static_cast<const TIO*>(a.s) + off;
   S.g = a.g ? static_cast<const TIO*>(a.g) + off * K : nullptr;
   S.v = a.v ? static_cast<const TIO*>(a.v) + off * K : nullptr;
+  S.n = n;
+  S.p = load_inst<K, TIO>(a, i);
+  return S;
+}
+
+// Source reading the wave's LDS slice: node i of the instance at global
+// row off is slice row off - lo + i.
+template <int K, int L, class TIO, int RHS, int OUT>
+__device__ __forceinline__ Src0<K, TIO, RHS> make_src0_lds(const Level0Args& a, int64_t i, int64_t off, int64_t n,
+                                                           int64_t lo, unsigned char* sl) {
+  using ST = Stage<K, L, TIO, RHS, OUT>;
+  Src0<K, TIO, RHS> S;
+  S.c = reinterpret_cast<const TIO*>(sl + ST::C);
+  S.s = reinterpret_cast<const TIO*>(sl + ST::S);
+  S.d = reinterpret_cast<const TIO*>(sl + ST::D);
+  S.g = reinterpret_cast<const TIO*>(sl + ST::G);
+  S.v = reinterpret_cast<const TIO*>(sl + ST::V);
+  S.o = off - lo;
   S.n = n;
   S.p = load_inst<K, TIO>(a, i);
   return S;
@@ -103,17 +203,29 @@ __device__ __forceinline__ void exchange_and_write(const Reduced<K>& red, bool w
 template <int K, int L, class TIO, int RHS, bool WREC>
 __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduce0(LevelDev l0, LevelDev l1, Level0Args a) {
   constexpr int REC = Dim<K>::Q + Dim<K>::KK;
+  using ST = Stage<K, L, TIO, RHS, OUT_STORE>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  unsigned char* sl = smem + (threadIdx.x / WAVE) * ST::BYTES;
   const int lane = lane_id();
   const int64_t G = l0.chunks;
   const int64_t tiles = G > 1 ? (G - 2) / (WAVE - 1) + 1 : 1;
-  for (int64_t tile = wave_id(); tile < tiles; tile += wave_count()) {
-    const int64_t g = tile * (WAVE - 1) + lane;
+  for (int64_t tile = wave_id(a); tile < tiles; tile += wave_count(a)) {
+    const int64_t g0 = tile * (WAVE - 1);
+    const int64_t g1 = g0 + WAVE < G ? g0 + WAVE : G;
+    // chunk metadata first: its loads then return ahead of the staged tile
+    const int64_t g = g0 + lane;
     const bool valid = g < G;
     const int64_t gg = valid ? g : G - 1;
     const int64_t inst = l0.chunk_inst[gg];
-    const int64_t j = gg - l0.chunk_off[inst];
+    int64_t lo, hi;
+    tile_rows(l0, g0, g1, l0.nodes, lo, hi);
+    const int64_t j0 = l0.chunk_off[inst];
     const int64_t off = l0.node_off[inst];
     const int64_t n = l0.node_off[inst + 1] - off;
+    const int64_t up0 = l1.node_off[inst];
+    const auto src = make_src0_lds<K, L, TIO, RHS, OUT_STORE>(a, inst, off, n, lo, sl);
+    stage_tile<K, L, TIO, RHS, OUT_STORE>(a, lo, hi, sl, lane);
+    const int64_t j = gg - j0;
     const ChunkGeom geo = chunk_geom(j, n, L);
     Reduced<K> red;
 #pragma unroll
@@ -123,13 +235,13 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduce0(LevelDev l0, Le
 #pragma unroll
     for (int e = 0; e < Dim<K>::KK; ++e) red.lB[e] = 0.0;
     red.fail = 0;
+    __builtin_amdgcn_s_waitcnt(0);
     if (valid && (geo.has_left || geo.has_right)) {
-      const auto S = make_src0<K, TIO, RHS>(a, inst, off, n);
-      reduce_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, red);
+      reduce_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, red);
       if (red.fail) report_fail(a, inst, 0, geo.a + red.fail - 1);
     }
     const bool writer = valid && lane > 0 && geo.has_left;
-    const int64_t node = writer ? l1.node_off[inst] + j - 1 : 0;
+    const int64_t node = writer ? up0 + j - 1 : 0;
     exchange_and_write<K>(red, writer, l1.rec + node * REC, l1.rhs + node * K, WREC);
   }
 }
@@ -141,7 +253,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduceN(LevelDev lv, Le
   const int lane = lane_id();
   const int64_t G = lv.chunks;
   const int64_t tiles = G > 1 ? (G - 2) / (WAVE - 1) + 1 : 1;
-  for (int64_t tile = wave_id(); tile < tiles; tile += wave_count()) {
+  for (int64_t tile = wave_id(a); tile < tiles; tile += wave_count(a)) {
     const int64_t g = tile * (WAVE - 1) + lane;
     const bool valid = g < G;
     const int64_t gg = valid ? g : G - 1;
@@ -179,7 +291,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsubN(LevelDev lv, L
   const int lane = lane_id();
   const int64_t G = lv.chunks;
   const int64_t tiles = (G + WAVE - 1) / WAVE;
-  for (int64_t tile = wave_id(); tile < tiles; tile += wave_count()) {
+  for (int64_t tile = wave_id(a); tile < tiles; tile += wave_count(a)) {
     const int64_t g = tile * WAVE + lane;
     if (g >= G) continue;
     const int64_t inst = lv.chunk_inst[g];
@@ -218,43 +330,58 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsubN(LevelDev lv, L
 template <int K, int L, class TIO, int RHS, int OUT>
 __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub0(LevelDev l0, LevelDev l1, bool has_next, Level0Args a) {
   constexpr bool ADD = (RHS == RHS_RESID || RHS == RHS_GRESID);
+  using ST = Stage<K, L, TIO, RHS, OUT>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  unsigned char* sl = smem + (threadIdx.x / WAVE) * ST::BYTES;
   const int lane = lane_id();
   const int64_t G = l0.chunks;
   const int64_t tiles = (G + WAVE - 1) / WAVE;
-  for (int64_t tile = wave_id(); tile < tiles; tile += wave_count()) {
-    const int64_t g = tile * WAVE + lane;
-    if (g >= G) continue;
-    const int64_t inst = l0.chunk_inst[g];
-    const int64_t j = g - l0.chunk_off[inst];
+  for (int64_t tile = wave_id(a); tile < tiles; tile += wave_count(a)) {
+    const int64_t g0 = tile * WAVE;
+    const int64_t g1 = g0 + WAVE < G ? g0 + WAVE : G;
+    // chunk metadata first: its loads then return ahead of the staged tile
+    const int64_t g = g0 + lane;
+    const bool valid = g < G;
+    const int64_t gg = valid ? g : G - 1;
+    const int64_t inst = l0.chunk_inst[gg];
+    int64_t lo, hi;
+    tile_rows(l0, g0, g1, l0.nodes, lo, hi);
+    const int64_t j0 = l0.chunk_off[inst];
     const int64_t off = l0.node_off[inst];
     const int64_t n = l0.node_off[inst + 1] - off;
+    const int64_t up0 = (has_next ? l1.node_off : l0.node_off)[inst];   // unconditional load
+    const auto src = make_src0_lds<K, L, TIO, RHS, OUT>(a, inst, off, n, lo, sl);
+    stage_tile<K, L, TIO, RHS, OUT>(a, lo, hi, sl, lane);
+    const int64_t j = gg - j0;
+    const int64_t up = has_next ? up0 : 0;
     const ChunkGeom geo = chunk_geom(j, n, L);
     double xl[K], xr[K], xs[L][K];
-    const int64_t up = has_next ? l1.node_off[inst] : 0;
 #pragma unroll
     for (int e = 0; e < K; ++e) {
-      xl[e] = geo.has_left ? l1.x[(up + j - 1) * K + e] : 0.0;
-      xr[e] = geo.has_right ? l1.x[(up + j) * K + e] : 0.0;
+      xl[e] = valid && geo.has_left ? l1.x[(up + j - 1) * K + e] : 0.0;
+      xr[e] = valid && geo.has_right ? l1.x[(up + j) * K + e] : 0.0;
     }
-    const auto S = make_src0<K, TIO, RHS>(a, inst, off, n);
-    const TIO* v = ADD ? static_cast<const TIO*>(a.v) + off * K : nullptr;
+    const TIO* vs = reinterpret_cast<const TIO*>(sl + ST::V);
+    __builtin_amdgcn_s_waitcnt(0);
+    if (!valid) continue;
     int fail;
     if (OUT == OUT_STORE) {
-      StoreSink<TIO, ADD> sink{static_cast<TIO*>(a.out) + off * K, v};
+      StoreSink<TIO, ADD> sink{static_cast<TIO*>(a.out) + off * K, vs, off - lo};
       if (geo.has_right) sink.template node<K>(geo.b + 1, xr);   // owned right separator
-      fail = backsub_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
+      fail = backsub_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
     } else {
       GradSink<K, TIO, ADD> sink;
-      sink.c = S.c; sink.d = S.d; sink.s = S.s;
-      sink.y = static_cast<const TIO*>(a.y) + off * K;
-      sink.v = v;
+      sink.c = src.c; sink.d = src.d; sink.s = src.s;
+      sink.y = reinterpret_cast<const TIO*>(sl + ST::Y);
+      sink.v = vs;
+      sink.o = off - lo;
       sink.dc = static_cast<TIO*>(a.dc) + off * K;
       sink.dd = static_cast<TIO*>(a.dd) + off;
       sink.ds = static_cast<TIO*>(a.ds) + off;
       sink.du0 = static_cast<TIO*>(a.du0) + inst * a.n_init;
-      sink.p = S.p;
+      sink.p = src.p;
       if (geo.has_right) sink.start(geo.b + 1, xr);
-      fail = backsub_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
+      fail = backsub_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
       if (geo.has_left) sink.left(geo.a - 1, xl);
       if (!geo.has_right) sink.ds[n - 1] = static_cast<TIO>(0.0);   // s of the last point is unused
 #pragma unroll
@@ -271,51 +398,99 @@ int64_t grid_for(int64_t tiles, const Launch& cfg) {
   return blocks < 1 ? 1 : blocks;
 }
 
+// Grid, workgroup and dynamic LDS of a level-0 launch: as many waves per
+// workgroup as cfg.block asks for and the per-workgroup LDS limit allows.
+template <int K, int L, class TIO, int RHS, int OUT>
+bool level0_grid(int64_t tiles, const Launch& cfg, dim3& grid, dim3& block, size_t& lds) {
+  constexpr size_t wb = Stage<K, L, TIO, RHS, OUT>::BYTES;
+  const int64_t fit = static_cast<int64_t>(cfg.lds_max) / static_cast<int64_t>(wb);
+  if (fit < 1) return false;
+  int wpb = cfg.block / WAVE;
+  if (wpb > fit) wpb = static_cast<int>(fit);
+  if (wpb < 1) wpb = 1;
+  Launch c = cfg;
+  c.block = wpb * WAVE;
+  grid = dim3(static_cast<unsigned>(grid_for(tiles, c)));
+  block = dim3(c.block);
+  lds = wb * wpb;
+  return true;
+}
+
+template <int K, int L, class TIO, int RHS, bool WREC>
+hipError_t launch_r0(const LevelDev& l0, const LevelDev& l1, const Level0Args& a, const Launch& cfg,
+                     hipStream_t st) {
+  const int64_t tiles = l0.chunks > 1 ? (l0.chunks - 2) / (WAVE - 1) + 1 : 1;
+  dim3 grid, block;
+  size_t lds;
+  if (!level0_grid<K, L, TIO, RHS, OUT_STORE>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
+  Level0Args b = a;
+  b.wpb = static_cast<int>(block.x) / WAVE;
+  b.nwaves = static_cast<int64_t>(grid.x) * b.wpb;
+  hipLaunchKernelGGL((k_reduce0<K, L, TIO, RHS, WREC>), grid, block, lds, st, l0, l1, b);
+  return hipGetLastError();
+}
+
+template <int K, int L, class TIO, int RHS, int OUT>
+hipError_t launch_b0(const LevelDev& l0, const LevelDev* l1, const Level0Args& a, const Launch& cfg,
+                     hipStream_t st) {
+  const int64_t tiles = (l0.chunks + WAVE - 1) / WAVE;
+  dim3 grid, block;
+  size_t lds;
+  if (!level0_grid<K, L, TIO, RHS, OUT>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
+  const LevelDev nx = l1 ? *l1 : LevelDev{};
+  Level0Args b = a;
+  b.wpb = static_cast<int>(block.x) / WAVE;
+  b.nwaves = static_cast<int64_t>(grid.x) * b.wpb;
+  hipLaunchKernelGGL((k_backsub0<K, L, TIO, RHS, OUT>), grid, block, lds, st, l0, nx, l1 != nullptr, b);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------- dispatchers
 template <int K, int L, class TIO>
 hipError_t reduce0_t(int rhs, bool wrec, const LevelDev& l0, const LevelDev& l1, const Level0Args& a,
                      const Launch& cfg, hipStream_t st) {
-  const int64_t tiles = l0.chunks > 1 ? (l0.chunks - 2) / (WAVE - 1) + 1 : 1;
-  const dim3 grid(static_cast<unsigned>(grid_for(tiles, cfg))), block(cfg.block);
   switch (rhs) {
     case RHS_BETA:
-      if (wrec) hipLaunchKernelGGL((k_reduce0<K, L, TIO, RHS_BETA, true>), grid, block, 0, st, l0, l1, a);
-      else hipLaunchKernelGGL((k_reduce0<K, L, TIO, RHS_BETA, false>), grid, block, 0, st, l0, l1, a);
-      break;
-    case RHS_RESID: hipLaunchKernelGGL((k_reduce0<K, L, TIO, RHS_RESID, false>), grid, block, 0, st, l0, l1, a); break;
+      return wrec ? launch_r0<K, L, TIO, RHS_BETA, true>(l0, l1, a, cfg, st)
+                  : launch_r0<K, L, TIO, RHS_BETA, false>(l0, l1, a, cfg, st);
+    case RHS_RESID: return launch_r0<K, L, TIO, RHS_RESID, false>(l0, l1, a, cfg, st);
     case RHS_G:
-      if (wrec) hipLaunchKernelGGL((k_reduce0<K, L, TIO, RHS_G, true>), grid, block, 0, st, l0, l1, a);
-      else hipLaunchKernelGGL((k_reduce0<K, L, TIO, RHS_G, false>), grid, block, 0, st, l0, l1, a);
-      break;
-    case RHS_GRESID: hipLaunchKernelGGL((k_reduce0<K, L, TIO, RHS_GRESID, false>), grid, block, 0, st, l0, l1, a); break;
+      return wrec ? launch_r0<K, L, TIO, RHS_G, true>(l0, l1, a, cfg, st)
+                  : launch_r0<K, L, TIO, RHS_G, false>(l0, l1, a, cfg, st);
+    case RHS_GRESID: return launch_r0<K, L, TIO, RHS_GRESID, false>(l0, l1, a, cfg, st);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <int K, int L, class TIO>
 hipError_t backsub0_t(int rhs, int out, const LevelDev& l0, const LevelDev* l1, const Level0Args& a,
                       const Launch& cfg, hipStream_t st) {
-  const int64_t tiles = (l0.chunks + WAVE - 1) / WAVE;
-  const dim3 grid(static_cast<unsigned>(grid_for(tiles, cfg))), block(cfg.block);
-  const LevelDev nx = l1 ? *l1 : LevelDev{};
-  const bool hn = l1 != nullptr;
   if (out == OUT_STORE) {
     switch (rhs) {
-      case RHS_BETA: hipLaunchKernelGGL((k_backsub0<K, L, TIO, RHS_BETA, OUT_STORE>), grid, block, 0, st, l0, nx, hn, a); break;
-      case RHS_RESID: hipLaunchKernelGGL((k_backsub0<K, L, TIO, RHS_RESID, OUT_STORE>), grid, block, 0, st, l0, nx, hn, a); break;
-      case RHS_G: hipLaunchKernelGGL((k_backsub0<K, L, TIO, RHS_G, OUT_STORE>), grid, block, 0, st, l0, nx, hn, a); break;
-      case RHS_GRESID: hipLaunchKernelGGL((k_backsub0<K, L, TIO, RHS_GRESID, OUT_STORE>), grid, block, 0, st, l0, nx, hn, a); break;
-      default: return hipErrorInvalidValue;
-    }
-  } else {
-    switch (rhs) {
-      case RHS_G: hipLaunchKernelGGL((k_backsub0<K, L, TIO, RHS_G, OUT_GRAD>), grid, block, 0, st, l0, nx, hn, a); break;
-      case RHS_GRESID: hipLaunchKernelGGL((k_backsub0<K, L, TIO, RHS_GRESID, OUT_GRAD>), grid, block, 0, st, l0, nx, hn, a); break;
+      case RHS_BETA: return launch_b0<K, L, TIO, RHS_BETA, OUT_STORE>(l0, l1, a, cfg, st);
+      case RHS_RESID: return launch_b0<K, L, TIO, RHS_RESID, OUT_STORE>(l0, l1, a, cfg, st);
+      case RHS_G: return launch_b0<K, L, TIO, RHS_G, OUT_STORE>(l0, l1, a, cfg, st);
+      case RHS_GRESID: return launch_b0<K, L, TIO, RHS_GRESID, OUT_STORE>(l0, l1, a, cfg, st);
       default: return hipErrorInvalidValue;
     }
   }
-  return hipGetLastError();
+  switch (rhs) {
+    case RHS_G: return launch_b0<K, L, TIO, RHS_G, OUT_GRAD>(l0, l1, a, cfg, st);
+    case RHS_GRESID: return launch_b0<K, L, TIO, RHS_GRESID, OUT_GRAD>(l0, l1, a, cfg, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int K, int L, class TIO>
+size_t lds_bytes_t(int rhs, int out) {
+  if (out == OUT_GRAD)
+    return rhs == RHS_GRESID ? Stage<K, L, TIO, RHS_GRESID, OUT_GRAD>::BYTES : Stage<K, L, TIO, RHS_G, OUT_GRAD>::BYTES;
+  switch (rhs) {
+    case RHS_BETA: return Stage<K, L, TIO, RHS_BETA, OUT_STORE>::BYTES;
+    case RHS_RESID: return Stage<K, L, TIO, RHS_RESID, OUT_STORE>::BYTES;
+    case RHS_G: return Stage<K, L, TIO, RHS_G, OUT_STORE>::BYTES;
+    default: return Stage<K, L, TIO, RHS_GRESID, OUT_STORE>::BYTES;
+  }
 }
 
 template <int K, int L>
@@ -323,8 +498,11 @@ hipError_t reduceN_t(bool wrec, int level, const LevelDev& l, const LevelDev& nx
                      const Launch& cfg, hipStream_t st) {
   const int64_t tiles = l.chunks > 1 ? (l.chunks - 2) / (WAVE - 1) + 1 : 1;
   const dim3 grid(static_cast<unsigned>(grid_for(tiles, cfg))), block(cfg.block);
-  if (wrec) hipLaunchKernelGGL((k_reduceN<K, L, true>), grid, block, 0, st, l, nx, a, level);
-  else hipLaunchKernelGGL((k_reduceN<K, L, false>), grid, block, 0, st, l, nx, a, level);
+  Level0Args b = a;
+  b.wpb = cfg.block / WAVE;
+  b.nwaves = static_cast<int64_t>(grid.x) * b.wpb;
+  if (wrec) hipLaunchKernelGGL((k_reduceN<K, L, true>), grid, block, 0, st, l, nx, b, level);
+  else hipLaunchKernelGGL((k_reduceN<K, L, false>), grid, block, 0, st, l, nx, b, level);
   return hipGetLastError();
 }
 
@@ -334,7 +512,10 @@ hipError_t backsubN_t(int level, const LevelDev& l, const LevelDev* nx, const Le
   const int64_t tiles = (l.chunks + WAVE - 1) / WAVE;
   const dim3 grid(static_cast<unsigned>(grid_for(tiles, cfg))), block(cfg.block);
   const LevelDev n2 = nx ? *nx : LevelDev{};
-  hipLaunchKernelGGL((k_backsubN<K, L>), grid, block, 0, st, l, n2, nx != nullptr, a, level);
+  Level0Args b = a;
+  b.wpb = cfg.block / WAVE;
+  b.nwaves = static_cast<int64_t>(grid.x) * b.wpb;
+  hipLaunchKernelGGL((k_backsubN<K, L>), grid, block, 0, st, l, n2, nx != nullptr, b, level);
   return hipGetLastError();
 }
 
@@ -357,6 +538,15 @@ bool SMNN_KFN(supported)(int K, int L) {
   SMNN_FOR_EACH_KL(X)
 #undef X
   return false;
+}
+
+size_t SMNN_KFN(level0_lds_bytes)(int K, int L, bool f32, int rhs_mode, int out_mode) {
+#define X(KV, LV)                                                                                    \
+  if (K == KV && L == LV)                                                                            \
+    return f32 ? lds_bytes_t<KV, LV, float>(rhs_mode, out_mode) : lds_bytes_t<KV, LV, double>(rhs_mode, out_mode);
+  SMNN_FOR_EACH_KL(X)
+#undef X
+  return 0;
 }
 
 hipError_t SMNN_KFN(launch_reduce0)(int K, int L, bool f32, int rhs_mode, bool write_rec, const LevelDev& l0,

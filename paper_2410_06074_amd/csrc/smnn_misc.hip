@@ -77,7 +77,8 @@ hipError_t launch_info_finalize(const Level0Args& a, int32_t* info, hipStream_t 
   hipError_t launch_reduceN_k##KV(int, int, bool, int, const LevelDev&, const LevelDev&, const Level0Args&, \
                                   const Launch&, hipStream_t);                                           \
   hipError_t launch_backsubN_k##KV(int, int, int, const LevelDev&, const LevelDev*, const Level0Args&,    \
-                                   const Launch&, hipStream_t);
+                                   const Launch&, hipStream_t);                                          \
+  size_t level0_lds_bytes_k##KV(int, int, bool, int, int);
 SMNN_DECL(2)
 SMNN_DECL(3)
 SMNN_DECL(4)
@@ -95,6 +96,11 @@ SMNN_DECL(5)
 bool supported(int K, int L) {
   SMNN_SWITCH(supported, K, L)
   return false;
+}
+
+size_t level0_lds_bytes(int K, int L, bool f32, int rhs_mode, int out_mode) {
+  SMNN_SWITCH(level0_lds_bytes, K, L, f32, rhs_mode, out_mode)
+  return 0;
 }
 
 hipError_t launch_reduce0(int K, int L, bool f32, int rhs_mode, bool write_rec, const LevelDev& l0,
