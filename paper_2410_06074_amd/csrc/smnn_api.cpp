@@ -39,7 +39,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 int default_chunk(int K, bool upper) {
   switch (K) {
     case 2: return 16;
-    case 3: return 8;
+    case 3: return upper ? 16 : 4;
     case 4: return upper ? 8 : 4;
     default: return 4;
   }
@@ -162,7 +162,7 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   p->L1 = L1;
   p->N = d->n_inst;
   p->f32 = d->mode == SMNN_MODE_FP32_REFINED;
-  p->cfg.block = d->block ? d->block : 256;
+  p->cfg.block = d->block ? d->block : 64;
   p->cfg.max_blocks = d->max_blocks;
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return SMNN_ERR_HIP; }
   int lds_max = 0;
@@ -473,7 +473,7 @@ smnn_status smnn_autotune(const smnn_plan_desc* desc, const void* c, const void*
     return SMNN_OK;
   };
   smnn_plan_desc d = *desc;
-  d.block = d.block ? d.block : 256;
+  d.block = d.block ? d.block : 64;
   const int chunks[] = {4, 8, 16};
   // 1. chunk lengths (level 0 x separator levels), default launch shape
   for (int l0 : chunks)

@@ -701,16 +701,17 @@ struct Src0 {
 // Level-0 solution sink: out_i = (v_i +) x_i in the I/O type.
 template <class TIO, bool ADD>
 struct StoreSink {
-  TIO* out;        // this instance's [n][K]
+  TIO* out;        // [..][K]: node i is row oo + i
   const TIO* v;    // previous iterate (ADD): node i is row vo + i
   int64_t vo = 0;
+  int64_t oo = 0;
   template <int K>
   SMNN_HD void node(int64_t i, const double (&x)[K]) {
 #pragma unroll
     for (int e = 0; e < K; ++e) {
       double val = x[e];
       if (ADD) val += static_cast<double>(v[(vo + i) * K + e]);
-      out[i * K + e] = static_cast<TIO>(val);
+      out[(oo + i) * K + e] = static_cast<TIO>(val);
     }
   }
 };
@@ -725,8 +726,9 @@ struct StoreSink {
 template <int K, class TIO, bool ADD>
 struct GradSink {
   const TIO *c, *d, *s, *y, *v;   // inputs: node i is row o + i
-  TIO *dc, *dd, *ds, *du0;        // outputs of this instance: node i is row i
-  int64_t o = 0;
+  TIO *dc, *dd, *ds;              // outputs: node i is row oo + i
+  TIO* du0;                       // this instance's [n_init]
+  int64_t o = 0, oo = 0;
   Inst<K> p;
   double lam_n[K], y_n[K];   // node i+1 (the one finished before)
   bool have_next = false;
@@ -749,8 +751,8 @@ struct GradSink {
       f = fma(cr, lam[r], f);
     }
 #pragma unroll
-    for (int r = 0; r < K; ++r) dc[i * K + r] = static_cast<TIO>(-wg2 * (e * lam[r] + f * yi[r]));
-    dd[i] = static_cast<TIO>(wg2 * f);
+    for (int r = 0; r < K; ++r) dc[(oo + i) * K + r] = static_cast<TIO>(-wg2 * (e * lam[r] + f * yi[r]));
+    dd[oo + i] = static_cast<TIO>(wg2 * f);
     dw[0] += -2.0 * p.wg * e * f;
     if (i == 0) {
 #pragma unroll
@@ -764,7 +766,7 @@ struct GradSink {
   SMNN_HD void pair(int64_t i, const double (&lam)[K], const double (&yi)[K]) {
     double g_s = 0.0, g_w = 0.0;
     pair_grad<K>(static_cast<double>(s[o + i]), p.ws, yi, y_n, lam, lam_n, g_s, g_w);
-    ds[i] = static_cast<TIO>(g_s);
+    ds[oo + i] = static_cast<TIO>(g_s);
     dw[2] += g_w;
   }
   // the chunk's right separator (owned; finished by the level above)

@@ -116,13 +116,26 @@ __device__ __forceinline__ void stage_tile(const Level0Args& a, int64_t lo, int6
 }
 
 // Rows of the tile of chunks [g0, g1): from the step before the first chunk
-// to the step after the last one, clipped to the arrays.
+// to the step after the last one, clipped to the arrays.  r0, r1: the rows
+// the chunks own (first row of g0, first row of g1).
 __device__ __forceinline__ void tile_rows(const LevelDev& l0, int64_t g0, int64_t g1, int64_t S, int64_t& lo,
-                                          int64_t& hi) {
-  lo = l0.chunk_step[g0] - 1;
-  hi = l0.chunk_step[g1] + 1;
-  if (lo < 0) lo = 0;
-  if (hi > S) hi = S;
+                                          int64_t& hi, int64_t& r0, int64_t& r1) {
+  r0 = l0.chunk_step[g0];
+  r1 = l0.chunk_step[g1];
+  lo = r0 > 0 ? r0 - 1 : 0;
+  hi = r1 + 1 < S ? r1 + 1 : S;
+}
+
+// Wave-cooperative copy of rows [r0, r1) (w elements each) from a slot of the
+// wave's LDS slice (slice row = global row - lo) to global memory: every
+// store instruction writes 64 consecutive elements.
+template <class T>
+__device__ __forceinline__ void unstage_rows(void* dst, int w, int64_t r0, int64_t r1, int64_t lo,
+                                             const unsigned char* slot, int lane) {
+  const T* l = reinterpret_cast<const T*>(slot) + (r0 - lo) * w;
+  T* g = static_cast<T*>(dst) + r0 * w;
+  const int n = static_cast<int>((r1 - r0) * w);
+  for (int k = lane; k < n; k += WAVE) g[k] = l[k];
 }
 
 template <int K, class TIO>
@@ -217,8 +230,8 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduce0(LevelDev l0, Le
     const bool valid = g < G;
     const int64_t gg = valid ? g : G - 1;
     const int64_t inst = l0.chunk_inst[gg];
-    int64_t lo, hi;
-    tile_rows(l0, g0, g1, l0.nodes, lo, hi);
+    int64_t lo, hi, r0, r1;
+    tile_rows(l0, g0, g1, l0.nodes, lo, hi, r0, r1);
     const int64_t j0 = l0.chunk_off[inst];
     const int64_t off = l0.node_off[inst];
     const int64_t n = l0.node_off[inst + 1] - off;
@@ -344,8 +357,8 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub0(LevelDev l0, L
     const bool valid = g < G;
     const int64_t gg = valid ? g : G - 1;
     const int64_t inst = l0.chunk_inst[gg];
-    int64_t lo, hi;
-    tile_rows(l0, g0, g1, l0.nodes, lo, hi);
+    int64_t lo, hi, r0, r1;
+    tile_rows(l0, g0, g1, l0.nodes, lo, hi, r0, r1);
     const int64_t j0 = l0.chunk_off[inst];
     const int64_t off = l0.node_off[inst];
     const int64_t n = l0.node_off[inst + 1] - off;
@@ -362,32 +375,53 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub0(LevelDev l0, L
       xr[e] = valid && geo.has_right ? l1.x[(up + j) * K + e] : 0.0;
     }
     const TIO* vs = reinterpret_cast<const TIO*>(sl + ST::V);
+    // ds rows of the tile: the step before each chunk (when it is in the
+    // same instance) through the chunk's last interior step, and an
+    // instance's last step in its last chunk
+    const int last = static_cast<int>(g1 - g0) - 1;
+    const bool first_starts = __shfl(static_cast<int>(j == 0), 0, WAVE) != 0;
+    const bool last_ends = __shfl(static_cast<int>(!geo.has_right), last, WAVE) != 0;
     __builtin_amdgcn_s_waitcnt(0);
-    if (!valid) continue;
-    int fail;
-    if (OUT == OUT_STORE) {
-      StoreSink<TIO, ADD> sink{static_cast<TIO*>(a.out) + off * K, vs, off - lo};
-      if (geo.has_right) sink.template node<K>(geo.b + 1, xr);   // owned right separator
-      fail = backsub_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
-    } else {
-      GradSink<K, TIO, ADD> sink;
-      sink.c = src.c; sink.d = src.d; sink.s = src.s;
-      sink.y = reinterpret_cast<const TIO*>(sl + ST::Y);
-      sink.v = vs;
-      sink.o = off - lo;
-      sink.dc = static_cast<TIO*>(a.dc) + off * K;
-      sink.dd = static_cast<TIO*>(a.dd) + off;
-      sink.ds = static_cast<TIO*>(a.ds) + off;
-      sink.du0 = static_cast<TIO*>(a.du0) + inst * a.n_init;
-      sink.p = src.p;
-      if (geo.has_right) sink.start(geo.b + 1, xr);
-      fail = backsub_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
-      if (geo.has_left) sink.left(geo.a - 1, xl);
-      if (!geo.has_right) sink.ds[n - 1] = static_cast<TIO>(0.0);   // s of the last point is unused
+    // Outputs go into the slice in place of inputs no lane reads afterwards
+    // (out / dc over c, dd over d, ds over s; a lane reads another lane's
+    // rows only for s, v, y of its left separator and v after its right
+    // one, before it writes anything), then out to HBM in whole rows.
+    if (valid) {
+      int fail;
+      if (OUT == OUT_STORE) {
+        StoreSink<TIO, ADD> sink{reinterpret_cast<TIO*>(sl + ST::C), vs, off - lo, off - lo};
+        if (geo.has_right) sink.template node<K>(geo.b + 1, xr);   // owned right separator
+        fail = backsub_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
+      } else {
+        GradSink<K, TIO, ADD> sink;
+        sink.c = src.c; sink.d = src.d; sink.s = src.s;
+        sink.y = reinterpret_cast<const TIO*>(sl + ST::Y);
+        sink.v = vs;
+        sink.o = off - lo;
+        sink.dc = reinterpret_cast<TIO*>(sl + ST::C);
+        sink.dd = reinterpret_cast<TIO*>(sl + ST::D);
+        sink.ds = reinterpret_cast<TIO*>(sl + ST::S);
+        sink.oo = off - lo;
+        sink.du0 = static_cast<TIO*>(a.du0) + inst * a.n_init;
+        sink.p = src.p;
+        if (geo.has_right) sink.start(geo.b + 1, xr);
+        fail = backsub_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
+        if (geo.has_left) sink.left(geo.a - 1, xl);
+        if (!geo.has_right) sink.ds[sink.oo + n - 1] = static_cast<TIO>(0.0);   // s of the last point is unused
 #pragma unroll
-      for (int e = 0; e < 3; ++e) a.dw_part[g * 3 + e] = sink.dw[e];
+        for (int e = 0; e < 3; ++e) a.dw_part[g * 3 + e] = sink.dw[e];
+      }
+      if (fail) report_fail(a, inst, 0, geo.a + fail - 1);
     }
-    if (fail) report_fail(a, inst, 0, geo.a + fail - 1);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    if (OUT == OUT_STORE) {
+      unstage_rows<TIO>(a.out, K, r0, r1, lo, sl + ST::C, lane);
+    } else {
+      unstage_rows<TIO>(a.dc, K, r0, r1, lo, sl + ST::C, lane);
+      unstage_rows<TIO>(a.dd, 1, r0, r1, lo, sl + ST::D, lane);
+      unstage_rows<TIO>(a.ds, 1, r0 - (first_starts ? 0 : 1), r1 - (last_ends ? 0 : 1), lo, sl + ST::S, lane);
+    }
   }
 }
 

@@ -32,7 +32,8 @@ def io_batch(bt, mode):
     return bt.astype(np.float32).astype(np.float64) if mode == "fp32r" else bt
 
 
-def run(bt, mode, gy=None, chunk=0, block=0, max_blocks=0, refine_steps=-1, device="cuda:0", info=True):
+def run(bt, mode, gy=None, chunk=0, block=0, max_blocks=0, refine_steps=-1, device="cuda:0", info=True,
+        chunk_upper=0):
     """Forward (and backward when gy is given) through the C-ABI; numpy results."""
     import torch
     from paper_2410_06074_amd import Plan
@@ -40,7 +41,7 @@ def run(bt, mode, gy=None, chunk=0, block=0, max_blocks=0, refine_steps=-1, devi
     dt = dtype_for(mode)
     steps = int(bt.T[0]) if np.all(bt.T == bt.T[0]) else bt.T
     p = Plan(bt.R, bt.n_init, bt.n_inst, steps, mode=mode, chunk=chunk, block=block, max_blocks=max_blocks,
-             refine_steps=refine_steps)
+             refine_steps=refine_steps, chunk_upper=chunk_upper)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
     c, b, h, u0, w = t(bt.c), t(bt.b), t(bt.h), t(bt.u0.reshape(bt.n_inst, bt.n_init)), t(bt.w)
     y = torch.empty((p.total_steps, p.k), dtype=dt, device=dev)

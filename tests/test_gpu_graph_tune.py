@@ -71,7 +71,8 @@ def test_autotuner_returns_a_working_mapping(tmp_path, monkeypatch):
     assert len(res["candidates"]) >= 4
     again = autotune(bt.R, bt.n_init, bt.n_inst, 500, "fp64r", *ins, gy, iters=2)
     assert again.get("cached") and again["chunk"] == res["chunk"]
-    out = H.run(bt, "fp64r", chunk=res["chunk"], block=res["block"], max_blocks=res["max_blocks"])
+    out = H.run(bt, "fp64r", chunk=res["chunk"], block=res["block"], max_blocks=res["max_blocks"],
+                chunk_upper=res["chunk_upper"])
     ref = banded.solve(bt)
     assert max(H.metrics.rel_by_order(out["y"], ref, bt.k)) < 1e-10
 
