@@ -85,6 +85,9 @@ struct Stage {
   static constexpr size_t V = G + (RD::g ? ROW_K : 0);
   static constexpr size_t Y = V + (RD::v ? ROW_K : 0);
   static constexpr size_t BYTES = Y + (RD::y ? ROW_K : 0);
+  // the reduce reuses the slice for the level-1 records it writes
+  static constexpr size_t RECOUT = sizeof(double) * WAVE * (Dim<K>::Q + Dim<K>::KK + K);
+  static constexpr size_t BYTES_REDUCE = BYTES > RECOUT ? BYTES : RECOUT;
 };
 
 // Wave-cooperative copy of rows [lo, hi) of an array with w elements per row
@@ -218,7 +221,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduce0(LevelDev l0, Le
   constexpr int REC = Dim<K>::Q + Dim<K>::KK;
   using ST = Stage<K, L, TIO, RHS, OUT_STORE>;
   extern __shared__ __align__(16) unsigned char smem[];
-  unsigned char* sl = smem + (threadIdx.x / WAVE) * ST::BYTES;
+  unsigned char* sl = smem + (threadIdx.x / WAVE) * ST::BYTES_REDUCE;
   const int lane = lane_id();
   const int64_t G = l0.chunks;
   const int64_t tiles = G > 1 ? (G - 2) / (WAVE - 1) + 1 : 1;
@@ -253,9 +256,34 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduce0(LevelDev l0, Le
       reduce_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, red);
       if (red.fail) report_fail(a, inst, 0, geo.a + red.fail - 1);
     }
+    // Level-1 records of the tile's separators: lane k > 0 combines its left
+    // separator from lane k-1's right half and its own left half.  The
+    // written nodes are consecutive; they are assembled in the (now unused)
+    // slice and stored as contiguous rows.
     const bool writer = valid && lane > 0 && geo.has_left;
     const int64_t node = writer ? up0 + j - 1 : 0;
-    exchange_and_write<K>(red, writer, l1.rec + node * REC, l1.rhs + node * K, WREC);
+    double rA[Dim<K>::Q], rf[K];
+#pragma unroll
+    for (int e = 0; e < Dim<K>::Q; ++e) rA[e] = __shfl_up(red.rA[e], 1, WAVE);
+#pragma unroll
+    for (int e = 0; e < K; ++e) rf[e] = __shfl_up(red.rf[e], 1, WAVE);
+    const uint64_t wmask = __ballot(writer);
+    if (wmask == 0) continue;
+    const int64_t n0 = __shfl(node, __builtin_ctzll(wmask), WAVE);
+    const int64_t n1 = __shfl(node, 63 - __builtin_clzll(wmask), WAVE) + 1;
+    double* orec = reinterpret_cast<double*>(sl);
+    double* orhs = orec + WAVE * REC;
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    if (writer) combine_separator<K>(rA, rf, red, orec + (node - n0) * REC, orhs + (node - n0) * K, WREC);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    if (WREC) {
+      const int nr = static_cast<int>((n1 - n0) * REC);
+      for (int k = lane; k < nr; k += WAVE) l1.rec[n0 * REC + k] = orec[k];
+    }
+    const int nf = static_cast<int>((n1 - n0) * K);
+    for (int k = lane; k < nf; k += WAVE) l1.rhs[n0 * K + k] = orhs[k];
   }
 }
 
@@ -434,9 +462,10 @@ int64_t grid_for(int64_t tiles, const Launch& cfg) {
 
 // Grid, workgroup and dynamic LDS of a level-0 launch: as many waves per
 // workgroup as cfg.block asks for and the per-workgroup LDS limit allows.
-template <int K, int L, class TIO, int RHS, int OUT>
+template <int K, int L, class TIO, int RHS, int OUT, bool REDUCE = false>
 bool level0_grid(int64_t tiles, const Launch& cfg, dim3& grid, dim3& block, size_t& lds) {
-  constexpr size_t wb = Stage<K, L, TIO, RHS, OUT>::BYTES;
+  using ST = Stage<K, L, TIO, RHS, OUT>;
+  constexpr size_t wb = REDUCE ? ST::BYTES_REDUCE : ST::BYTES;
   const int64_t fit = static_cast<int64_t>(cfg.lds_max) / static_cast<int64_t>(wb);
   if (fit < 1) return false;
   int wpb = cfg.block / WAVE;
@@ -456,7 +485,7 @@ hipError_t launch_r0(const LevelDev& l0, const LevelDev& l1, const Level0Args& a
   const int64_t tiles = l0.chunks > 1 ? (l0.chunks - 2) / (WAVE - 1) + 1 : 1;
   dim3 grid, block;
   size_t lds;
-  if (!level0_grid<K, L, TIO, RHS, OUT_STORE>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
+  if (!level0_grid<K, L, TIO, RHS, OUT_STORE, true>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
   Level0Args b = a;
   b.wpb = static_cast<int>(block.x) / WAVE;
   b.nwaves = static_cast<int64_t>(grid.x) * b.wpb;
@@ -519,11 +548,11 @@ template <int K, int L, class TIO>
 size_t lds_bytes_t(int rhs, int out) {
   if (out == OUT_GRAD)
     return rhs == RHS_GRESID ? Stage<K, L, TIO, RHS_GRESID, OUT_GRAD>::BYTES : Stage<K, L, TIO, RHS_G, OUT_GRAD>::BYTES;
-  switch (rhs) {
-    case RHS_BETA: return Stage<K, L, TIO, RHS_BETA, OUT_STORE>::BYTES;
-    case RHS_RESID: return Stage<K, L, TIO, RHS_RESID, OUT_STORE>::BYTES;
-    case RHS_G: return Stage<K, L, TIO, RHS_G, OUT_STORE>::BYTES;
-    default: return Stage<K, L, TIO, RHS_GRESID, OUT_STORE>::BYTES;
+  switch (rhs) {   // the reduce and the storing back-substitution of the form
+    case RHS_BETA: return Stage<K, L, TIO, RHS_BETA, OUT_STORE>::BYTES_REDUCE;
+    case RHS_RESID: return Stage<K, L, TIO, RHS_RESID, OUT_STORE>::BYTES_REDUCE;
+    case RHS_G: return Stage<K, L, TIO, RHS_G, OUT_STORE>::BYTES_REDUCE;
+    default: return Stage<K, L, TIO, RHS_GRESID, OUT_STORE>::BYTES_REDUCE;
   }
 }
 
