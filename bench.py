@@ -186,12 +186,57 @@ def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0, graph=
             "err": err, "levels": plan.levels, "chunk": [plan.chunk, plan.chunk_upper], "refine": plan.refine_steps}
 
 
+KERNEL_SOURCES = ("smnn_kernels.hip", "smnn_core.h", "smnn_internal.h")
+
+
+def kernel_sources_sha256():
+    """Digest of the kernel sources: a measured counter value is only reported
+    for the kernels it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2410_06074_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summaries
+    (profiles/*.md lines 'traffic <kernel> bytes_per_launch=<B>
+    kernel_sources_sha256=<digest>'), or None if none was taken on the
+    current kernel sources."""
+    import glob
+    import re
+    digest = kernel_sources_sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for m in re.finditer(r"^traffic (\S+) bytes_per_launch=(\d+) kernel_sources_sha256=([0-9a-f]+)",
+                                 f.read(), re.M):
+                if m.group(1) == kernel and m.group(3) == digest:
+                    return int(m.group(2))
+    return None
+
+
+def copy_calibration():
+    """Plain device-to-device copy of a known size: the reference the HBM byte
+    counters (FETCH_SIZE, WRITE_SIZE) are scaled by."""
+    import torch
+    n = 64 * 1024 * 1024                      # 64 Mi doubles = 512 MiB each way
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_direction": n * 8, "copies": 3}), flush=True)
+    return 0
+
+
 def roofline(res):
     dom_key, dom = max(res["per_kind"].items(), key=lambda kv: kv[1]["ms"])
     avg_ms = dom["ms"] / dom["n"]
     achieved = dom["bytes"] / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": dom_key, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dom_key),
             "bytes_per_launch": int(dom["bytes"]), "avg_launch_ms": round(avg_ms, 5),
             "share_of_step": round(dom["ms"] / max(1e-9, sum(v["ms"] for v in res["per_kind"].values())), 3)}
 
@@ -234,7 +279,11 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of hipGraph replays")
     ap.add_argument("--autotune", action="store_true", help="pick the launch mapping with smnn_autotune first")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: library default)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 512 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solve is per-instance independent and this build has no "
               "multi-GPU path (see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
