@@ -39,7 +39,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 int default_chunk(int K, bool upper) {
   switch (K) {
     case 2: return 16;
-    case 3: return upper ? 16 : 4;
+    case 3: return upper ? 8 : 4;
     case 4: return upper ? 8 : 4;
     default: return 4;
   }
@@ -191,9 +191,13 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   // factor: level >= 1 node records
   size_t fb = 0;
   p->rec_off.assign(lv.size(), 0);
+  // separator levels use the interleaved layout: TILE_W chunks x L1 slots per group
+  auto slots = [&](size_t l) {
+    return static_cast<size_t>((lv[l].chunks + TILE_W - 1) / TILE_W) * TILE_W * L1;
+  };
   for (size_t l = 1; l < lv.size(); ++l) {
     p->rec_off[l] = fb;
-    fb = align_up(fb + sizeof(double) * REC * lv[l].nodes);
+    fb = align_up(fb + sizeof(double) * REC * slots(l));
   }
   // workspace: level >= 1 rhs and solution, two iterate buffers, chunk partials, info
   size_t wb = 0;
@@ -201,7 +205,7 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   p->x_off.assign(lv.size(), 0);
   for (size_t l = 1; l < lv.size(); ++l) {
     p->rhs_off[l] = wb;
-    wb = align_up(wb + sizeof(double) * K * lv[l].nodes);
+    wb = align_up(wb + sizeof(double) * K * slots(l));
     p->x_off[l] = wb;
     wb = align_up(wb + sizeof(double) * K * lv[l].nodes);
   }

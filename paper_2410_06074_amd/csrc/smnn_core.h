@@ -820,6 +820,71 @@ struct SrcN {
   }
 };
 
+// Separator levels store node records interleaved by groups of W = 8
+// chunks: field e (of F) of node u of chunk C (global chunk index at that
+// level, chunk length L) sits at ((C / W) L + u) F W + W e + C % W.  The
+// lanes of a wave own consecutive chunks, so one field of their u-th nodes
+// is 64 doubles in whole 64-byte runs, and the reduce below, which writes a
+// few consecutive chunks' records, writes whole 64-byte runs too.  An
+// instance's last chunk may leave slots unused.
+constexpr int TILE_W = 8;
+SMNN_HD int64_t tpos(int64_t C, int64_t u, int L, int F, int e) {
+  return ((C / TILE_W) * L + u) * (TILE_W * F) + TILE_W * e + (C % TILE_W);
+}
+
+// Node data of a separator level in the interleaved layout, seen from
+// the lane that owns chunk C (first node a, instance-relative): nodes a..a+L-1
+// are in chunk C, node a-1 is the last node of chunk C-1.
+template <int K>
+struct SrcT {
+  const double* rec;  // records, F = Q + KK: {A packed, B = block (node+1, node)}
+  const double* rhs;  // right-hand sides, F = K
+  int64_t C, a;
+  int L;
+  SMNN_HD void where(int64_t i, int64_t& c, int64_t& u) const {
+    c = i >= a ? C : C - 1;
+    u = i >= a ? i - a : L - 1;
+  }
+  SMNN_HD void load(int64_t i, double (&A)[Dim<K>::Q], double (&f)[K], double (&Bp)[Dim<K>::KK]) const {
+    constexpr int R = Dim<K>::Q + Dim<K>::KK;
+    int64_t c, u;
+    where(i, c, u);
+#pragma unroll
+    for (int e = 0; e < Dim<K>::Q; ++e) A[e] = rec[tpos(c, u, L, R, e)];
+#pragma unroll
+    for (int e = 0; e < K; ++e) f[e] = rhs[tpos(c, u, L, K, e)];
+    if (i > 0) {
+      int64_t cp, up;
+      where(i - 1, cp, up);
+#pragma unroll
+      for (int e = 0; e < Dim<K>::KK; ++e) Bp[e] = rec[tpos(cp, up, L, R, Dim<K>::Q + e)];
+    }
+  }
+  SMNN_HD void coupling(int64_t i, double (&B)[Dim<K>::KK]) const {
+    constexpr int R = Dim<K>::Q + Dim<K>::KK;
+    int64_t c, u;
+    where(i, c, u);
+#pragma unroll
+    for (int e = 0; e < Dim<K>::KK; ++e) B[e] = rec[tpos(c, u, L, R, Dim<K>::Q + e)];
+  }
+};
+
+// combine_separator for the interleaved layout: the node is node u of
+// chunk C of its level (chunk length L).
+template <int K>
+SMNN_HD void combine_separator_t(const double (&rA)[Dim<K>::Q], const double (&rf)[K], const Reduced<K>& lh,
+                                 double* rec, double* rhs, int64_t C, int64_t u, int L, bool write_rec) {
+  constexpr int Q = Dim<K>::Q, KK = Dim<K>::KK;
+  if (write_rec) {
+#pragma unroll
+    for (int e = 0; e < Q; ++e) rec[tpos(C, u, L, Q + KK, e)] = rA[e] + lh.lA[e];
+#pragma unroll
+    for (int e = 0; e < KK; ++e) rec[tpos(C, u, L, Q + KK, Q + e)] = lh.lB[e];
+  }
+#pragma unroll
+  for (int e = 0; e < K; ++e) rhs[tpos(C, u, L, K, e)] = rf[e] + lh.lf[e];
+}
+
 // Record of a separator node combined from the two chunks that share it:
 // rh = reduction of the chunk on its left (which owns it), lh = reduction of
 // the chunk on its right.

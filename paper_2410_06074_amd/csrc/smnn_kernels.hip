@@ -85,9 +85,6 @@ struct Stage {
   static constexpr size_t V = G + (RD::g ? ROW_K : 0);
   static constexpr size_t Y = V + (RD::v ? ROW_K : 0);
   static constexpr size_t BYTES = Y + (RD::y ? ROW_K : 0);
-  // the reduce reuses the slice for the level-1 records it writes
-  static constexpr size_t RECOUT = sizeof(double) * WAVE * (Dim<K>::Q + Dim<K>::KK + K);
-  static constexpr size_t BYTES_REDUCE = BYTES > RECOUT ? BYTES : RECOUT;
 };
 
 // Wave-cooperative copy of rows [lo, hi) of an array with w elements per row
@@ -202,17 +199,19 @@ __device__ __forceinline__ void report_fail(const Level0Args& a, int64_t inst, i
 }
 
 // Exchange the right-separator reduction of lane-1 and write the combined
-// separator record.  All 64 lanes must call this.
+// record of this lane's left separator, node m (instance-relative) of the
+// next level, in that level's interleaved layout (chunk_off0 = the
+// instance's first chunk there).  All 64 lanes must call this.
 template <int K>
-__device__ __forceinline__ void exchange_and_write(const Reduced<K>& red, bool writer, double* rec, double* rhs,
-                                                   bool write_rec) {
+__device__ __forceinline__ void exchange_and_write(const Reduced<K>& red, bool writer, const LevelDev& nx,
+                                                   int64_t chunk_off0, int64_t m, int L1, bool write_rec) {
   constexpr int Q = Dim<K>::Q;
   double rA[Q], rf[K];
 #pragma unroll
   for (int e = 0; e < Q; ++e) rA[e] = __shfl_up(red.rA[e], 1, WAVE);
 #pragma unroll
   for (int e = 0; e < K; ++e) rf[e] = __shfl_up(red.rf[e], 1, WAVE);
-  if (writer) combine_separator<K>(rA, rf, red, rec, rhs, write_rec);
+  if (writer) combine_separator_t<K>(rA, rf, red, nx.rec, nx.rhs, chunk_off0 + m / L1, m % L1, L1, write_rec);
 }
 
 // ------------------------------------------------------------ level 0 reduce
@@ -221,7 +220,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduce0(LevelDev l0, Le
   constexpr int REC = Dim<K>::Q + Dim<K>::KK;
   using ST = Stage<K, L, TIO, RHS, OUT_STORE>;
   extern __shared__ __align__(16) unsigned char smem[];
-  unsigned char* sl = smem + (threadIdx.x / WAVE) * ST::BYTES_REDUCE;
+  unsigned char* sl = smem + (threadIdx.x / WAVE) * ST::BYTES;
   const int lane = lane_id();
   const int64_t G = l0.chunks;
   const int64_t tiles = G > 1 ? (G - 2) / (WAVE - 1) + 1 : 1;
@@ -238,7 +237,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduce0(LevelDev l0, Le
     const int64_t j0 = l0.chunk_off[inst];
     const int64_t off = l0.node_off[inst];
     const int64_t n = l0.node_off[inst + 1] - off;
-    const int64_t up0 = l1.node_off[inst];
+    const int64_t c1 = l1.chunk_off[inst];
     const auto src = make_src0_lds<K, L, TIO, RHS, OUT_STORE>(a, inst, off, n, lo, sl);
     stage_tile<K, L, TIO, RHS, OUT_STORE>(a, lo, hi, sl, lane);
     const int64_t j = gg - j0;
@@ -256,41 +255,14 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduce0(LevelDev l0, Le
       reduce_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, red);
       if (red.fail) report_fail(a, inst, 0, geo.a + red.fail - 1);
     }
-    // Level-1 records of the tile's separators: lane k > 0 combines its left
-    // separator from lane k-1's right half and its own left half.  The
-    // written nodes are consecutive; they are assembled in the (now unused)
-    // slice and stored as contiguous rows.
     const bool writer = valid && lane > 0 && geo.has_left;
-    const int64_t node = writer ? up0 + j - 1 : 0;
-    double rA[Dim<K>::Q], rf[K];
-#pragma unroll
-    for (int e = 0; e < Dim<K>::Q; ++e) rA[e] = __shfl_up(red.rA[e], 1, WAVE);
-#pragma unroll
-    for (int e = 0; e < K; ++e) rf[e] = __shfl_up(red.rf[e], 1, WAVE);
-    const uint64_t wmask = __ballot(writer);
-    if (wmask == 0) continue;
-    const int64_t n0 = __shfl(node, __builtin_ctzll(wmask), WAVE);
-    const int64_t n1 = __shfl(node, 63 - __builtin_clzll(wmask), WAVE) + 1;
-    double* orec = reinterpret_cast<double*>(sl);
-    double* orhs = orec + WAVE * REC;
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-    if (writer) combine_separator<K>(rA, rf, red, orec + (node - n0) * REC, orhs + (node - n0) * K, WREC);
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-    if (WREC) {
-      const int nr = static_cast<int>((n1 - n0) * REC);
-      for (int k = lane; k < nr; k += WAVE) l1.rec[n0 * REC + k] = orec[k];
-    }
-    const int nf = static_cast<int>((n1 - n0) * K);
-    for (int k = lane; k < nf; k += WAVE) l1.rhs[n0 * K + k] = orhs[k];
+    exchange_and_write<K>(red, writer, l1, c1, j - 1, a.L1, WREC);
   }
 }
 
 // -------------------------------------------------------- level >= 1 reduce
 template <int K, int L, bool WREC>
 __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduceN(LevelDev lv, LevelDev nx, Level0Args a, int level) {
-  constexpr int REC = Dim<K>::Q + Dim<K>::KK;
   const int lane = lane_id();
   const int64_t G = lv.chunks;
   const int64_t tiles = G > 1 ? (G - 2) / (WAVE - 1) + 1 : 1;
@@ -311,16 +283,19 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduceN(LevelDev lv, Le
 #pragma unroll
     for (int e = 0; e < Dim<K>::KK; ++e) red.lB[e] = 0.0;
     red.fail = 0;
+    const int64_t c1 = nx.chunk_off[inst];
     if (valid && (geo.has_left || geo.has_right)) {
-      SrcN<K> S;
-      S.rec = lv.rec + off * REC;
-      S.rhs = lv.rhs + off * K;
+      SrcT<K> S;
+      S.rec = lv.rec;
+      S.rhs = lv.rhs;
+      S.C = gg;
+      S.a = geo.a;
+      S.L = L;
       reduce_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, red);
       if (red.fail) report_fail(a, inst, level, geo.a + red.fail - 1);
     }
     const bool writer = valid && lane > 0 && geo.has_left;
-    const int64_t node = writer ? nx.node_off[inst] + j - 1 : 0;
-    exchange_and_write<K>(red, writer, nx.rec + node * REC, nx.rhs + node * K, WREC);
+    exchange_and_write<K>(red, writer, nx, c1, j - 1, L, WREC);
   }
 }
 
@@ -328,7 +303,6 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduceN(LevelDev lv, Le
 template <int K, int L>
 __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsubN(LevelDev lv, LevelDev nx, bool has_next, Level0Args a,
                                                  int level) {
-  constexpr int REC = Dim<K>::Q + Dim<K>::KK;
   const int lane = lane_id();
   const int64_t G = lv.chunks;
   const int64_t tiles = (G + WAVE - 1) / WAVE;
@@ -347,9 +321,12 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsubN(LevelDev lv, L
       xl[e] = geo.has_left ? nx.x[(up + j - 1) * K + e] : 0.0;
       xr[e] = geo.has_right ? nx.x[(up + j) * K + e] : 0.0;
     }
-    SrcN<K> S;
-    S.rec = lv.rec + off * REC;
-    S.rhs = lv.rhs + off * K;
+    SrcT<K> S;
+    S.rec = lv.rec;
+    S.rhs = lv.rhs;
+    S.C = g;
+    S.a = geo.a;
+    S.L = L;
     const int fail = backsub_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs);
     if (fail) report_fail(a, inst, level, geo.a + fail - 1);
     double* x = lv.x + off * K;
@@ -462,10 +439,9 @@ int64_t grid_for(int64_t tiles, const Launch& cfg) {
 
 // Grid, workgroup and dynamic LDS of a level-0 launch: as many waves per
 // workgroup as cfg.block asks for and the per-workgroup LDS limit allows.
-template <int K, int L, class TIO, int RHS, int OUT, bool REDUCE = false>
+template <int K, int L, class TIO, int RHS, int OUT>
 bool level0_grid(int64_t tiles, const Launch& cfg, dim3& grid, dim3& block, size_t& lds) {
-  using ST = Stage<K, L, TIO, RHS, OUT>;
-  constexpr size_t wb = REDUCE ? ST::BYTES_REDUCE : ST::BYTES;
+  constexpr size_t wb = Stage<K, L, TIO, RHS, OUT>::BYTES;
   const int64_t fit = static_cast<int64_t>(cfg.lds_max) / static_cast<int64_t>(wb);
   if (fit < 1) return false;
   int wpb = cfg.block / WAVE;
@@ -485,7 +461,7 @@ hipError_t launch_r0(const LevelDev& l0, const LevelDev& l1, const Level0Args& a
   const int64_t tiles = l0.chunks > 1 ? (l0.chunks - 2) / (WAVE - 1) + 1 : 1;
   dim3 grid, block;
   size_t lds;
-  if (!level0_grid<K, L, TIO, RHS, OUT_STORE, true>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
+  if (!level0_grid<K, L, TIO, RHS, OUT_STORE>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
   Level0Args b = a;
   b.wpb = static_cast<int>(block.x) / WAVE;
   b.nwaves = static_cast<int64_t>(grid.x) * b.wpb;
@@ -548,11 +524,11 @@ template <int K, int L, class TIO>
 size_t lds_bytes_t(int rhs, int out) {
   if (out == OUT_GRAD)
     return rhs == RHS_GRESID ? Stage<K, L, TIO, RHS_GRESID, OUT_GRAD>::BYTES : Stage<K, L, TIO, RHS_G, OUT_GRAD>::BYTES;
-  switch (rhs) {   // the reduce and the storing back-substitution of the form
-    case RHS_BETA: return Stage<K, L, TIO, RHS_BETA, OUT_STORE>::BYTES_REDUCE;
-    case RHS_RESID: return Stage<K, L, TIO, RHS_RESID, OUT_STORE>::BYTES_REDUCE;
-    case RHS_G: return Stage<K, L, TIO, RHS_G, OUT_STORE>::BYTES_REDUCE;
-    default: return Stage<K, L, TIO, RHS_GRESID, OUT_STORE>::BYTES_REDUCE;
+  switch (rhs) {
+    case RHS_BETA: return Stage<K, L, TIO, RHS_BETA, OUT_STORE>::BYTES;
+    case RHS_RESID: return Stage<K, L, TIO, RHS_RESID, OUT_STORE>::BYTES;
+    case RHS_G: return Stage<K, L, TIO, RHS_G, OUT_STORE>::BYTES;
+    default: return Stage<K, L, TIO, RHS_GRESID, OUT_STORE>::BYTES;
   }
 }
 
