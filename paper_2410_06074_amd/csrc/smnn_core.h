@@ -505,15 +505,17 @@ struct NoSink {
 };
 
 // Solve the chunk interior a..b with the separator values xl (node a-1) and
-// xr (node b+1) known.  x[u] receives node a+u for u = 0..b-a (it first holds
-// the forward-substituted right-hand sides, then the solution); sink.node(i,
-// x_i) is called as each node is finished, in decreasing order of i.
-template <int K, int L, class Src, class Sink = NoSink>
-SMNN_HD int backsub_chunk(const Src& src, int64_t a, int64_t b, bool has_left, bool has_right,
-                          const double (&xl)[K], const double (&xr)[K], double (&x)[L][K],
-                          Sink&& sink = Sink()) {
+// xr (node b+1) known, in two sweeps.  The forward sweep factors the interior
+// (Ls[u] = Cholesky factor of node a+u's reduced diagonal block) and leaves
+// the forward-substituted right-hand sides in x; the backward sweep turns x
+// into the solution, x[u] = node a+u for u = 0..b-a, and calls sink.node(i,
+// x_i) as each node is finished, in decreasing order of i.  Returns the
+// chunk-relative node + 1 of the first non-positive pivot, 0 if none.
+template <int K, int L, class Src>
+SMNN_HD int backsub_forward(const Src& src, int64_t a, int64_t b, bool has_left, bool has_right,
+                            const double (&xl)[K], const double (&xr)[K], double (&Ls)[L][Dim<K>::Q],
+                            double (&x)[L][K]) {
   constexpr int Q = Dim<K>::Q, KK = Dim<K>::KK;
-  double Ls[L][Q];
   int fail = 0;
 #pragma unroll
   for (int u = 0; u < L; ++u) {
@@ -546,6 +548,13 @@ SMNN_HD int backsub_chunk(const Src& src, int64_t a, int64_t b, bool has_left, b
 #pragma unroll
     for (int e = 0; e < K; ++e) x[u][e] = f[e];
   }
+  return fail;
+}
+
+template <int K, int L, class Src, class Sink = NoSink>
+SMNN_HD void backsub_backward(const Src& src, int64_t a, int64_t b, const double (&Ls)[L][Dim<K>::Q],
+                              double (&x)[L][K], Sink&& sink = Sink()) {
+  constexpr int KK = Dim<K>::KK;
 #pragma unroll
   for (int u = L - 1; u >= 0; --u) {
     const int64_t i = a + u;
@@ -563,6 +572,15 @@ SMNN_HD int backsub_chunk(const Src& src, int64_t a, int64_t b, bool has_left, b
     usolve<K>(Ls[u], x[u]);                    // x_i = L^{-T}(ghat_i - L^{-1} B_i^T x_{i+1})
     sink.template node<K>(i, x[u]);
   }
+}
+
+template <int K, int L, class Src, class Sink = NoSink>
+SMNN_HD int backsub_chunk(const Src& src, int64_t a, int64_t b, bool has_left, bool has_right,
+                          const double (&xl)[K], const double (&xr)[K], double (&x)[L][K],
+                          Sink&& sink = Sink()) {
+  double Ls[L][Dim<K>::Q];
+  const int fail = backsub_forward<K, L>(src, a, b, has_left, has_right, xl, xr, Ls, x);
+  backsub_backward<K, L>(src, a, b, Ls, x, static_cast<Sink&&>(sink));
   return fail;
 }
 

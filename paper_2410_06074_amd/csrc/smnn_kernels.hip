@@ -66,7 +66,7 @@ struct Reads {
   static constexpr bool d = RHS == RHS_BETA || RHS == RHS_RESID || OUT == OUT_GRAD;
   static constexpr bool g = RHS == RHS_G || RHS == RHS_GRESID;
   static constexpr bool v = RHS == RHS_RESID || RHS == RHS_GRESID;
-  static constexpr bool y = OUT == OUT_GRAD;
+  static constexpr bool y = OUT == OUT_GRAD;   // staged after the forward sweep, over g
 };
 
 // Byte layout of one wave's LDS slice: ROWS steps of each array read, every
@@ -83,8 +83,8 @@ struct Stage {
   static constexpr size_t D = S + ROW_1;
   static constexpr size_t G = D + (RD::d ? ROW_1 : 0);
   static constexpr size_t V = G + (RD::g ? ROW_K : 0);
-  static constexpr size_t Y = V + (RD::v ? ROW_K : 0);
-  static constexpr size_t BYTES = Y + (RD::y ? ROW_K : 0);
+  static constexpr size_t Y = G;   // dl/dy is read by the forward sweep only
+  static constexpr size_t BYTES = V + (RD::v ? ROW_K : 0);
 };
 
 // Wave-cooperative copy of rows [lo, hi) of an array with w elements per row
@@ -112,7 +112,6 @@ __device__ __forceinline__ void stage_tile(const Level0Args& a, int64_t lo, int6
   if (RD::d) stage_rows<TIO>(a.d, 1, lo, hi, sl + ST::D, lane);
   if (RD::g) stage_rows<TIO>(a.g, K, lo, hi, sl + ST::G, lane);
   if (RD::v) stage_rows<TIO>(a.v, K, lo, hi, sl + ST::V, lane);
-  if (RD::y) stage_rows<TIO>(a.y, K, lo, hi, sl + ST::Y, lane);
 }
 
 // Rows of the tile of chunks [g0, g1): from the step before the first chunk
@@ -391,13 +390,24 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub0(LevelDev l0, L
     // (out / dc over c, dd over d, ds over s; a lane reads another lane's
     // rows only for s, v, y of its left separator and v after its right
     // one, before it writes anything), then out to HBM in whole rows.
-    if (valid) {
-      int fail;
-      if (OUT == OUT_STORE) {
-        StoreSink<TIO, ADD> sink{reinterpret_cast<TIO*>(sl + ST::C), vs, off - lo, off - lo};
-        if (geo.has_right) sink.template node<K>(geo.b + 1, xr);   // owned right separator
-        fail = backsub_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
-      } else {
+    if (OUT == OUT_STORE && valid) {
+      StoreSink<TIO, ADD> sink{reinterpret_cast<TIO*>(sl + ST::C), vs, off - lo, off - lo};
+      if (geo.has_right) sink.template node<K>(geo.b + 1, xr);   // owned right separator
+      const int fail = backsub_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
+      if (fail) report_fail(a, inst, 0, geo.a + fail - 1);
+    }
+    if (OUT == OUT_GRAD) {
+      // forward sweep; then y (read only by the gradient formation) is staged
+      // over dl/dy, which only the forward sweep reads; then the backward
+      // sweep forms the gradients
+      double Ls[L][Dim<K>::Q];
+      int fail = 0;
+      if (valid) fail = backsub_forward<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, Ls, xs);
+      __builtin_amdgcn_wave_barrier();
+      stage_rows<TIO>(a.y, K, lo, hi, sl + ST::Y, lane);
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+      if (valid) {
         GradSink<K, TIO, ADD> sink;
         sink.c = src.c; sink.d = src.d; sink.s = src.s;
         sink.y = reinterpret_cast<const TIO*>(sl + ST::Y);
@@ -410,13 +420,13 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub0(LevelDev l0, L
         sink.du0 = static_cast<TIO*>(a.du0) + inst * a.n_init;
         sink.p = src.p;
         if (geo.has_right) sink.start(geo.b + 1, xr);
-        fail = backsub_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
+        backsub_backward<K, L>(src, geo.a, geo.b, Ls, xs, sink);
         if (geo.has_left) sink.left(geo.a - 1, xl);
         if (!geo.has_right) sink.ds[sink.oo + n - 1] = static_cast<TIO>(0.0);   // s of the last point is unused
 #pragma unroll
         for (int e = 0; e < 3; ++e) a.dw_part[g * 3 + e] = sink.dw[e];
+        if (fail) report_fail(a, inst, 0, geo.a + fail - 1);
       }
-      if (fail) report_fail(a, inst, 0, geo.a + fail - 1);
     }
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
