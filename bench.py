@@ -66,6 +66,9 @@ def kernel_bytes(rec, plan, io):
             + (K if rhs in (RHS_RESID, RHS_GRESID) else 0) + (K if grad else 0)
         wr = (K + 2) * S * io + G0 * 3 * 8 + N * plan.n_init * io if grad else K * S * io
         return S * el * io + per_inst + n(1) * K * 8 + wr
+    if kind == "backsub_reduce0":          # rhs = the solve's form (beta or dl/dy)
+        el = K + 1 + (1 if rhs == RHS_BETA else 0) + (K if rhs == RHS_G else 0)
+        return S * el * io + per_inst + n(1) * K * 8 + K * S * io + n(1) * K * 8
     if kind == "dw_reduce":
         return G0 * 3 * 8 + N * 3 * io
     return 0

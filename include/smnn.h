@@ -171,6 +171,7 @@ typedef struct {
 #define SMNN_K_BACKSUB0 4
 #define SMNN_K_DW 5
 #define SMNN_K_INFO 6
+#define SMNN_K_BACKSUB_REDUCE0 7   /* level-0 back-substitution fused with the next solve's level-0 reduce */
 smnn_status smnn_trace_enable(smnn_plan* plan, int32_t capacity);
 int32_t smnn_trace_read(smnn_plan* plan, smnn_trace_record* out, int32_t cap);
 

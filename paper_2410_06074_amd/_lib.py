@@ -27,7 +27,8 @@ class TraceRecord(ctypes.Structure):
                 ("out", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
-KERNEL_NAMES = {1: "reduce0", 2: "reduceN", 3: "backsubN", 4: "backsub0", 5: "dw_reduce", 6: "info"}
+KERNEL_NAMES = {1: "reduce0", 2: "reduceN", 3: "backsubN", 4: "backsub0", 5: "dw_reduce", 6: "info",
+                7: "backsub_reduce0"}
 
 
 class TuneResult(ctypes.Structure):

@@ -98,13 +98,15 @@ struct Tracer {
     if (e_ != hipSuccess) return SMNN_ERR_HIP;              \
   } while (0)
 
-// One solve of M x = f through every level.  rhs selects f; the level-0
-// back-substitution writes `a.out` (OUT_STORE) or the gradients (OUT_GRAD).
-smnn_status solve(const smnn_plan* p, const Bound& b, int rhs, bool write_rec, int out_mode,
-                  const Level0Args& a, hipStream_t st) {
+// The part of a solve of M x = f above the level-0 back-substitution: the
+// level-0 reduce (unless skip_reduce0: a fused kernel already wrote the
+// level-1 right-hand sides), the reduces of levels >= 1 up and their
+// back-substitutions down.
+smnn_status solve_upper(const smnn_plan* p, const Bound& b, int rhs, bool write_rec, const Level0Args& a,
+                        hipStream_t st, bool skip_reduce0 = false) {
   const int nl = static_cast<int>(b.lev.size());
   const Tracer tr{p, st};
-  if (nl > 1)
+  if (nl > 1 && !skip_reduce0)
     SMNN_LAUNCH(tr, SMNN_K_REDUCE0, 0, rhs, 0,
                 launch_reduce0(p->K, p->L0, p->f32, rhs, write_rec, b.lev[0], b.lev[1], a, p->cfg, st));
   for (int l = 1; l + 1 < nl; ++l)
@@ -113,9 +115,38 @@ smnn_status solve(const smnn_plan* p, const Bound& b, int rhs, bool write_rec, i
   for (int l = nl - 1; l >= 1; --l)
     SMNN_LAUNCH(tr, SMNN_K_BACKSUBN, l, rhs, 0,
                 launch_backsubN(p->K, p->L1, l, b.lev[l], l + 1 < nl ? &b.lev[l + 1] : nullptr, a, p->cfg, st));
+  return SMNN_OK;
+}
+
+smnn_status backsub0(const smnn_plan* p, const Bound& b, int rhs, int out_mode, const Level0Args& a,
+                     hipStream_t st) {
+  const int nl = static_cast<int>(b.lev.size());
+  const Tracer tr{p, st};
   SMNN_LAUNCH(tr, SMNN_K_BACKSUB0, 0, rhs, out_mode,
               launch_backsub0(p->K, p->L0, p->f32, rhs, out_mode, b.lev[0], nl > 1 ? &b.lev[1] : nullptr, a,
                               p->cfg, st));
+  return SMNN_OK;
+}
+
+// One solve of M x = f through every level.  rhs selects f; the level-0
+// back-substitution writes `a.out` (OUT_STORE) or the gradients (OUT_GRAD).
+smnn_status solve(const smnn_plan* p, const Bound& b, int rhs, bool write_rec, int out_mode,
+                  const Level0Args& a, hipStream_t st) {
+  const smnn_status s = solve_upper(p, b, rhs, write_rec, a, st);
+  if (s != SMNN_OK) return s;
+  return backsub0(p, b, rhs, out_mode, a, st);
+}
+
+// A solve with right-hand side rhs (beta or dl/dy) storing its iterate to
+// a.out, whose level-0 back-substitution also does the level-0 reduce of
+// the first refinement solve (needs a level 1).
+smnn_status solve_then_reduce(const smnn_plan* p, const Bound& b, int rhs, bool write_rec, const Level0Args& a,
+                              hipStream_t st) {
+  const smnn_status s = solve_upper(p, b, rhs, write_rec, a, st);
+  if (s != SMNN_OK) return s;
+  const Tracer tr{p, st};
+  SMNN_LAUNCH(tr, SMNN_K_BACKSUB_REDUCE0, 0, rhs, 0,
+              launch_backsub_reduce0(p->K, p->L0, p->f32, rhs, b.lev[0], b.lev[1], a, p->cfg, st));
   return SMNN_OK;
 }
 
@@ -345,13 +376,19 @@ smnn_status smnn_forward(const smnn_plan* p, const void* c, const void* b, const
   a.N = p->N;
   a.info = info ? bd.info : nullptr;
   SMNN_HIP(launch_info_init(a, st));
+  const bool fused = p->refine > 0 && bd.lev.size() > 1;
   a.out = p->refine == 0 ? y : bd.buf[0];
-  smnn_status s = solve(p, bd, RHS_BETA, true, OUT_STORE, a, st);
+  smnn_status s = fused ? solve_then_reduce(p, bd, RHS_BETA, true, a, st) : solve(p, bd, RHS_BETA, true, OUT_STORE, a, st);
   if (s != SMNN_OK) return s;
   for (int m = 1; m <= p->refine; ++m) {
     a.v = a.out;
     a.out = (m == p->refine) ? y : bd.buf[m % 2];
-    s = solve(p, bd, RHS_RESID, false, OUT_STORE, a, st);
+    if (m == 1 && fused) {
+      s = solve_upper(p, bd, RHS_RESID, false, a, st, true);
+      if (s == SMNN_OK) s = backsub0(p, bd, RHS_RESID, OUT_STORE, a, st);
+    } else {
+      s = solve(p, bd, RHS_RESID, false, OUT_STORE, a, st);
+    }
     if (s != SMNN_OK) return s;
   }
   SMNN_HIP(launch_info_finalize(a, info, st));
@@ -386,14 +423,20 @@ smnn_status smnn_backward(const smnn_plan* p, const void* c, const void* b, cons
     s = solve(p, bd, RHS_G, false, OUT_GRAD, a, st);
     if (s != SMNN_OK) return s;
   } else {
+    const bool fused = bd.lev.size() > 1;
     a.out = bd.buf[0];
-    s = solve(p, bd, RHS_G, false, OUT_STORE, a, st);
+    s = fused ? solve_then_reduce(p, bd, RHS_G, false, a, st) : solve(p, bd, RHS_G, false, OUT_STORE, a, st);
     if (s != SMNN_OK) return s;
     for (int m = 1; m <= p->refine; ++m) {
       a.v = a.out;
       const bool lastm = m == p->refine;
       a.out = lastm ? nullptr : bd.buf[m % 2];
-      s = solve(p, bd, RHS_GRESID, false, lastm ? OUT_GRAD : OUT_STORE, a, st);
+      if (m == 1 && fused) {
+        s = solve_upper(p, bd, RHS_GRESID, false, a, st, true);
+        if (s == SMNN_OK) s = backsub0(p, bd, RHS_GRESID, lastm ? OUT_GRAD : OUT_STORE, a, st);
+      } else {
+        s = solve(p, bd, RHS_GRESID, false, lastm ? OUT_GRAD : OUT_STORE, a, st);
+      }
       if (s != SMNN_OK) return s;
     }
   }

@@ -63,6 +63,12 @@ hipError_t launch_backsubN(int K, int L, int level, const LevelDev& l, const Lev
                            const Level0Args& a, const Launch& cfg, hipStream_t st);
 hipError_t launch_backsub0(int K, int L, bool f32, int rhs_mode, int out_mode, const LevelDev& l0,
                            const LevelDev* l1, const Level0Args& a, const Launch& cfg, hipStream_t st);
+// Level-0 back-substitution of a solve with right-hand side rhs_in (beta or
+// dl/dy), storing the iterate to a.out, fused with the level-0 reduce of the
+// refinement solve that follows (residual or adjoint residual of that
+// iterate; writes the level-1 right-hand sides only).
+hipError_t launch_backsub_reduce0(int K, int L, bool f32, int rhs_in, const LevelDev& l0, const LevelDev& l1,
+                                  const Level0Args& a, const Launch& cfg, hipStream_t st);
 hipError_t launch_dw_reduce(bool f32, const LevelDev& l0, const Level0Args& a, hipStream_t st);
 hipError_t launch_info_init(const Level0Args& a, hipStream_t st);
 

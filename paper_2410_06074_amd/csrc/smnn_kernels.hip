@@ -172,10 +172,10 @@ __device__ __forceinline__ Src0<K, TIO, RHS> make_src0(const Level0Args& a, int6
 
 // Source reading the wave's LDS slice: node i of the instance at global
 // row off is slice row off - lo + i.
-template <int K, int L, class TIO, int RHS, int OUT>
+template <int K, int L, class TIO, int RHS, int OUT, int LRHS = RHS>
 __device__ __forceinline__ Src0<K, TIO, RHS> make_src0_lds(const Level0Args& a, int64_t i, int64_t off, int64_t n,
                                                            int64_t lo, unsigned char* sl) {
-  using ST = Stage<K, L, TIO, RHS, OUT>;
+  using ST = Stage<K, L, TIO, LRHS, OUT>;   // slice layout of the variant LRHS
   Src0<K, TIO, RHS> S;
   S.c = reinterpret_cast<const TIO*>(sl + ST::C);
   S.s = reinterpret_cast<const TIO*>(sl + ST::S);
@@ -440,6 +440,94 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub0(LevelDev l0, L
   }
 }
 
+// ------------------------------- level 0: back-substitution + next reduce
+// The level-0 back-substitution of one solve fused with the level-0 reduce
+// of the refinement solve that follows it (RIN = beta, ROUT = residual; or
+// RIN = dl/dy, ROUT = adjoint residual).  The new iterate stays in the LDS
+// slice, where the residual reduce reads it, so that reduce re-reads no
+// input from HBM.  A tile owns 62 chunks; lane 0 back-substitutes and
+// reduces the previous tile's last owned chunk (each separator is combined
+// from the chunks on both of its sides) and lane 63 back-substitutes the
+// next tile's first chunk (the residual at a chunk's right separator needs
+// the iterate one step past it).
+template <int K, int L, class TIO, int RIN, int ROUT>
+__global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDev l0, LevelDev l1, Level0Args a) {
+  using ST = Stage<K, L, TIO, ROUT, OUT_STORE>;   // c, h, (b | dl/dy) staged; the iterate in the v slot
+  constexpr int OWN = WAVE - 2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  unsigned char* sl = smem + (threadIdx.x / WAVE) * ST::BYTES;
+  TIO* it = reinterpret_cast<TIO*>(sl + ST::V);
+  const int lane = lane_id();
+  const int64_t G = l0.chunks;
+  const int64_t tiles = (G + OWN - 1) / OWN;
+  for (int64_t tile = wave_id(a); tile < tiles; tile += wave_count(a)) {
+    const int64_t t0 = tile * OWN;                   // owned chunks [t0, t1)
+    const int64_t t1 = t0 + OWN < G ? t0 + OWN : G;
+    const int64_t gb = t0 > 0 ? t0 - 1 : 0;          // tile chunks [gb, ge)
+    const int64_t ge = t1 < G ? t1 + 1 : G;
+    const int64_t g = t0 - 1 + lane;
+    const bool valid = g >= gb && g < ge;
+    const bool owned = g >= t0 && g < t1;
+    const int64_t gg = valid ? g : (g < gb ? gb : ge - 1);
+    const int64_t inst = l0.chunk_inst[gg];
+    int64_t lo, hi, r0, r1;
+    tile_rows(l0, gb, ge, l0.nodes, lo, hi, r0, r1);
+    const int64_t o0 = l0.chunk_step[t0], o1 = l0.chunk_step[t1];   // owned rows
+    const int64_t j0 = l0.chunk_off[inst];
+    const int64_t off = l0.node_off[inst];
+    const int64_t n = l0.node_off[inst + 1] - off;
+    const int64_t up0 = (l1.node_off ? l1.node_off : l0.node_off)[inst];
+    const int64_t c1 = (l1.chunk_off ? l1.chunk_off : l0.chunk_off)[inst];
+    const auto src = make_src0_lds<K, L, TIO, RIN, OUT_STORE, ROUT>(a, inst, off, n, lo, sl);
+    stage_rows<TIO>(a.c, K, lo, hi, sl + ST::C, lane);
+    stage_rows<TIO>(a.s, 1, lo, hi, sl + ST::S, lane);
+    if (RIN == RHS_BETA) stage_rows<TIO>(a.d, 1, lo, hi, sl + ST::D, lane);
+    if (RIN == RHS_G) stage_rows<TIO>(a.g, K, lo, hi, sl + ST::G, lane);
+    const int64_t j = gg - j0;
+    const ChunkGeom geo = chunk_geom(j, n, L);
+    double xl[K], xr[K], xs[L][K];
+#pragma unroll
+    for (int e = 0; e < K; ++e) {
+      xl[e] = valid && geo.has_left ? l1.x[(up0 + j - 1) * K + e] : 0.0;
+      xr[e] = valid && geo.has_right ? l1.x[(up0 + j) * K + e] : 0.0;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    // 1. back-substitution: the iterate of every tile chunk into the slice
+    //    (lane 0 also stores its left separator's value, the step before the
+    //    tile, which its residual reads)
+    if (valid) {
+      StoreSink<TIO, false> sink{it, nullptr, src.o, src.o};
+      if (geo.has_right) sink.template node<K>(geo.b + 1, xr);
+      if (lane == 0 && geo.has_left) sink.template node<K>(geo.a - 1, xl);
+      const int fail = backsub_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
+      if (fail) report_fail(a, inst, 0, geo.a + fail - 1);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    // 2. reduce with the residual of that iterate as right-hand side
+    Src0<K, TIO, ROUT> rs;
+    rs.c = src.c; rs.d = src.d; rs.s = src.s; rs.g = src.g; rs.v = it;
+    rs.n = src.n; rs.o = src.o; rs.p = src.p;
+    Reduced<K> red;
+#pragma unroll
+    for (int e = 0; e < Dim<K>::Q; ++e) { red.rA[e] = 0.0; red.lA[e] = 0.0; }
+#pragma unroll
+    for (int e = 0; e < K; ++e) { red.rf[e] = 0.0; red.lf[e] = 0.0; }
+#pragma unroll
+    for (int e = 0; e < Dim<K>::KK; ++e) red.lB[e] = 0.0;
+    red.fail = 0;
+    if (valid && g < t1 && (geo.has_left || geo.has_right)) {
+      reduce_chunk<K, L>(rs, geo.a, geo.b, geo.has_left, geo.has_right, red);
+      if (red.fail) report_fail(a, inst, 0, geo.a + red.fail - 1);
+    }
+    exchange_and_write<K>(red, owned && geo.has_left, l1, c1, j - 1, a.L1, false);
+    // 3. the owned chunks' iterate out to HBM in whole rows
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    unstage_rows<TIO>(a.out, K, o0, o1, lo, sl + ST::V, lane);
+  }
+}
+
 int64_t grid_for(int64_t tiles, const Launch& cfg) {
   const int64_t waves_per_block = cfg.block / WAVE;
   int64_t blocks = (tiles + waves_per_block - 1) / waves_per_block;
@@ -494,6 +582,20 @@ hipError_t launch_b0(const LevelDev& l0, const LevelDev* l1, const Level0Args& a
   return hipGetLastError();
 }
 
+template <int K, int L, class TIO, int RIN, int ROUT>
+hipError_t launch_br0(const LevelDev& l0, const LevelDev& l1, const Level0Args& a, const Launch& cfg,
+                      hipStream_t st) {
+  const int64_t tiles = (l0.chunks + WAVE - 3) / (WAVE - 2);
+  dim3 grid, block;
+  size_t lds;
+  if (!level0_grid<K, L, TIO, ROUT, OUT_STORE>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
+  Level0Args b = a;
+  b.wpb = static_cast<int>(block.x) / WAVE;
+  b.nwaves = static_cast<int64_t>(grid.x) * b.wpb;
+  hipLaunchKernelGGL((k_backsub_reduce0<K, L, TIO, RIN, ROUT>), grid, block, lds, st, l0, l1, b);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------- dispatchers
 template <int K, int L, class TIO>
 hipError_t reduce0_t(int rhs, bool wrec, const LevelDev& l0, const LevelDev& l1, const Level0Args& a,
@@ -526,6 +628,16 @@ hipError_t backsub0_t(int rhs, int out, const LevelDev& l0, const LevelDev* l1, 
   switch (rhs) {
     case RHS_G: return launch_b0<K, L, TIO, RHS_G, OUT_GRAD>(l0, l1, a, cfg, st);
     case RHS_GRESID: return launch_b0<K, L, TIO, RHS_GRESID, OUT_GRAD>(l0, l1, a, cfg, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int K, int L, class TIO>
+hipError_t backsub_reduce0_t(int rhs_in, const LevelDev& l0, const LevelDev& l1, const Level0Args& a,
+                             const Launch& cfg, hipStream_t st) {
+  switch (rhs_in) {
+    case RHS_BETA: return launch_br0<K, L, TIO, RHS_BETA, RHS_RESID>(l0, l1, a, cfg, st);
+    case RHS_G: return launch_br0<K, L, TIO, RHS_G, RHS_GRESID>(l0, l1, a, cfg, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -615,6 +727,18 @@ hipError_t SMNN_KFN(launch_backsub0)(int K, int L, bool f32, int rhs_mode, int o
   if (K == KV && L == LV)                                                                            \
     return f32 ? backsub0_t<KV, LV, float>(rhs_mode, out_mode, l0, l1, a, cfg, st)                  \
                : backsub0_t<KV, LV, double>(rhs_mode, out_mode, l0, l1, a, cfg, st);
+  SMNN_FOR_EACH_KL(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t SMNN_KFN(launch_backsub_reduce0)(int K, int L, bool f32, int rhs_in, const LevelDev& l0,
+                                            const LevelDev& l1, const Level0Args& a, const Launch& cfg,
+                                            hipStream_t st) {
+#define X(KV, LV)                                                                                    \
+  if (K == KV && L == LV)                                                                            \
+    return f32 ? backsub_reduce0_t<KV, LV, float>(rhs_in, l0, l1, a, cfg, st)                       \
+               : backsub_reduce0_t<KV, LV, double>(rhs_in, l0, l1, a, cfg, st);
   SMNN_FOR_EACH_KL(X)
 #undef X
   return hipErrorInvalidValue;

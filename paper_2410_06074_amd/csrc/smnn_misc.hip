@@ -78,7 +78,9 @@ hipError_t launch_info_finalize(const Level0Args& a, int32_t* info, hipStream_t 
                                   const Launch&, hipStream_t);                                           \
   hipError_t launch_backsubN_k##KV(int, int, int, const LevelDev&, const LevelDev*, const Level0Args&,    \
                                    const Launch&, hipStream_t);                                          \
-  size_t level0_lds_bytes_k##KV(int, int, bool, int, int);
+  size_t level0_lds_bytes_k##KV(int, int, bool, int, int);                                                \
+  hipError_t launch_backsub_reduce0_k##KV(int, int, bool, int, const LevelDev&, const LevelDev&,          \
+                                          const Level0Args&, const Launch&, hipStream_t);
 SMNN_DECL(2)
 SMNN_DECL(3)
 SMNN_DECL(4)
@@ -112,6 +114,12 @@ hipError_t launch_reduce0(int K, int L, bool f32, int rhs_mode, bool write_rec, 
 hipError_t launch_backsub0(int K, int L, bool f32, int rhs_mode, int out_mode, const LevelDev& l0,
                            const LevelDev* l1, const Level0Args& a, const Launch& cfg, hipStream_t st) {
   SMNN_SWITCH(launch_backsub0, K, L, f32, rhs_mode, out_mode, l0, l1, a, cfg, st)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_backsub_reduce0(int K, int L, bool f32, int rhs_in, const LevelDev& l0, const LevelDev& l1,
+                                  const Level0Args& a, const Launch& cfg, hipStream_t st) {
+  SMNN_SWITCH(launch_backsub_reduce0, K, L, f32, rhs_in, l0, l1, a, cfg, st)
   return hipErrorInvalidValue;
 }
 

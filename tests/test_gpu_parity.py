@@ -195,3 +195,31 @@ def test_workspace_too_small_is_rejected():
     with pytest.raises(SmnnError) as e:
         p.forward(t(bt.c), t(bt.b), t(bt.h), t(bt.u0), t(bt.w), y, p.new_factor(dev), small)
     assert e.value.status == 3
+
+
+# ------------------------------------------- refinement step counts 0, 1, 2
+@pytest.mark.parametrize("mode", ["fp64r", "fp32r"])
+def test_refinement_steps(mode):
+    # several levels (T up to 2000 with chunks 4 / 8) and, separately, a batch
+    # whose instances are all a single level-0 chunk (no separator level)
+    for T in ([2000, 1, 37, 512, 1999], [1, 2, 3, 4, 4]):
+        bt = H.io_batch(gaussian_batch(len(T), T, R=2, seed=77 + len(T) + T[-1], weights=(0.9, 1.2, 1.4)), mode)
+        gy = np.random.default_rng(5).standard_normal(bt.c.shape)
+        if mode == "fp32r":
+            gy = gy.astype(np.float32).astype(np.float64)
+        ref = banded.grad(bt, gy)
+        kappa = banded.cond(bt).max()
+        errs = []
+        for steps in (0, 1, 2):
+            out = H.run(bt, mode, gy, chunk=4, chunk_upper=8, refine_steps=steps)
+            assert out["plan"].refine_steps == steps
+            worst = H.compare(bt, out, ref, range(bt.n_inst))
+            errs.append(worst)
+            _print("refine %s T=%s steps=%d" % (mode, T, steps), " ".join("%s=%.1e" % kv for kv in worst.items()))
+            if steps == 0:
+                assert worst["y"] <= H.y_tolerance("fp64", kappa) if mode == "fp64r" else worst["y"] <= 1e-3
+            else:
+                assert worst["y"] <= H.y_tolerance(mode, kappa)
+                for key in ("dc", "dd", "ds", "du0", "dw"):
+                    assert worst[key] <= H.g_tolerance(mode, kappa), key
+        assert errs[2]["y"] <= max(2 * errs[1]["y"], 1e-13)
