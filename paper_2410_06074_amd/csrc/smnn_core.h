@@ -814,8 +814,10 @@ struct GradSink {
   }
 };
 
-// Node data of a reduced (separator) level: records written by the level
-// below.  rec[node] = {A packed (Q), B = block (node+1, node) (K*K)}.
+// Node data of a reduced (separator) level in the natural layout (one record
+// per node, as the host checker in tests/emu keeps them; the kernels use the
+// interleaved layout of SrcT): rec[node] = {A packed (Q), B = block
+// (node+1, node) (K*K)}.
 template <int K>
 struct SrcN {
   const double* rec;  // [n][Q + KK] of this instance
@@ -903,9 +905,9 @@ SMNN_HD void combine_separator_t(const double (&rA)[Dim<K>::Q], const double (&r
   for (int e = 0; e < K; ++e) rhs[tpos(C, u, L, K, e)] = rf[e] + lh.lf[e];
 }
 
-// Record of a separator node combined from the two chunks that share it:
-// rh = reduction of the chunk on its left (which owns it), lh = reduction of
-// the chunk on its right.
+// Record of a separator node combined from the two chunks that share it
+// (natural layout): rh = reduction of the chunk on its left (which owns it),
+// lh = reduction of the chunk on its right.
 template <int K>
 SMNN_HD void combine_separator(const double (&rA)[Dim<K>::Q], const double (&rf)[K],
                                const Reduced<K>& lh, double* rec, double* rhs, bool write_rec) {

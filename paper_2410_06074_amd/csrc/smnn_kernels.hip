@@ -26,9 +26,14 @@
 // every per-step array they read into the wave's slice of LDS, with
 // direct global-to-LDS loads that all lanes issue at once; the chunk
 // recurrences then read LDS.  A wave thus waits on HBM about once per tile
-// rather than once per node, which is what bounds the per-lane sequential
-// recurrences otherwise (a 64-lane wave holds a few hundred bytes of loads
-// in flight per node step).
+// rather than once per node step.  The level-0 back-substitution writes its
+// results into the slice and stores them as whole rows.  In the refined
+// modes the back-substitution of the first solve also performs the level-0
+// reduce of the refinement solve (k_backsub_reduce0), from the iterate it
+// leaves in LDS.  Separator levels keep their records interleaved by groups
+// of chunks (tpos in smnn_core.h), so their per-lane node loads are
+// contiguous across the lanes of a wave.
+
 #include <hip/hip_runtime.h>
 
 #include "smnn_core.h"
