@@ -378,7 +378,8 @@ smnn_status smnn_forward(const smnn_plan* p, const void* c, const void* b, const
   SMNN_HIP(launch_info_init(a, st));
   const bool fused = p->refine > 0 && bd.lev.size() > 1;
   a.out = p->refine == 0 ? y : bd.buf[0];
-  smnn_status s = fused ? solve_then_reduce(p, bd, RHS_BETA, true, a, st) : solve(p, bd, RHS_BETA, true, OUT_STORE, a, st);
+  smnn_status s = fused ? solve_then_reduce(p, bd, RHS_BETA, true, a, st)
+                        : solve(p, bd, RHS_BETA, true, OUT_STORE, a, st);
   if (s != SMNN_OK) return s;
   for (int m = 1; m <= p->refine; ++m) {
     a.v = a.out;
@@ -425,7 +426,8 @@ smnn_status smnn_backward(const smnn_plan* p, const void* c, const void* b, cons
   } else {
     const bool fused = bd.lev.size() > 1;
     a.out = bd.buf[0];
-    s = fused ? solve_then_reduce(p, bd, RHS_G, false, a, st) : solve(p, bd, RHS_G, false, OUT_STORE, a, st);
+    s = fused ? solve_then_reduce(p, bd, RHS_G, false, a, st)
+              : solve(p, bd, RHS_G, false, OUT_STORE, a, st);
     if (s != SMNN_OK) return s;
     for (int m = 1; m <= p->refine; ++m) {
       a.v = a.out;

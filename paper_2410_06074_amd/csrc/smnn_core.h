@@ -40,14 +40,6 @@ struct Dim {
 
 SMNN_HD constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// Keeps the compiler from hoisting a node's loads above the previous node's
-// arithmetic (which would hold a whole chunk of inputs in registers).
-#if defined(__HIP_DEVICE_COMPILE__) && defined(SMNN_NODE_FENCE)
-#define SMNN_FENCE() asm volatile("" ::: "memory")
-#else
-#define SMNN_FENCE() do {} while (0)
-#endif
-
 // Compile-time coefficients of the smoothness blocks.  With S+ = diag(s^r),
 // F_{ij} = 1/(j-i)! (j >= i) as in App. A.2, every entry of the three blocks
 // a pair of neighbouring nodes contributes is w_s^2 s^{i+j} times a constant:
@@ -448,7 +440,6 @@ SMNN_HD void reduce_chunk(const Src& src, int64_t a, int64_t b, bool has_left, b
   for (int u = 0; u < L; ++u) {
     const int64_t i = a + u;
     if (i > b) break;
-    SMNN_FENCE();
     double A[Q], f[K], Bp[KK];
     src.load(i, A, f, Bp);                     // Bp = B_{i-1} (block (i, i-1)) when i > 0
     double D[Q], X[KK];
@@ -521,7 +512,6 @@ SMNN_HD int backsub_forward(const Src& src, int64_t a, int64_t b, bool has_left,
   for (int u = 0; u < L; ++u) {
     const int64_t i = a + u;
     if (i > b) break;
-    SMNN_FENCE();
     double A[Q], f[K], Bp[KK];
     src.load(i, A, f, Bp);                     // Bp = B_{i-1} when i > 0
     if (u == 0 && has_left) sub_matvec<K>(Bp, xl, f);   // f_a -= B_{a-1} x_{a-1}

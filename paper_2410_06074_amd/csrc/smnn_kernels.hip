@@ -350,7 +350,8 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsubN(LevelDev lv, L
 
 // ------------------------------------------------------- level 0 back-subst.
 template <int K, int L, class TIO, int RHS, int OUT>
-__global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub0(LevelDev l0, LevelDev l1, bool has_next, Level0Args a) {
+__global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub0(LevelDev l0, LevelDev l1, bool has_next,
+                                                                  Level0Args a) {
   constexpr bool ADD = (RHS == RHS_RESID || RHS == RHS_GRESID);
   using ST = Stage<K, L, TIO, RHS, OUT>;
   extern __shared__ __align__(16) unsigned char smem[];
