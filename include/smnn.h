@@ -101,7 +101,7 @@ typedef struct {
   int64_t steps_uniform;
   int32_t mode;           /* smnn_mode */
   int32_t refine_steps;   /* refinement steps in the refined modes, 0..2; -1: default (1) */
-  int32_t chunk;          /* nodes per lane at level 0 (time steps; 4, 8 or 16); 0: default for the order */
+  int32_t chunk;          /* nodes per lane at level 0 (time steps; 4, 8 or 16); 0: default for the order and mode */
   int32_t chunk_upper;    /* nodes per lane at the separator levels >= 1; 0: default for the order */
   int32_t block;          /* threads per workgroup (64..256, multiple of 64); 0: 64 */
   int32_t max_blocks;     /* >0: persistent grid-stride launch with at most this many
