@@ -15,7 +15,13 @@ Prints ONE JSON line (rank 0).  Besides the contract fields it carries
   cpu_baseline  the oracle (oracle/banded.c, OpenMP) timed on a bounded
                 sample of the same workload on the host's cores;
   modes         steps/s, ms/step and sampled error against the FP64 oracle
-                for every solver mode measured (the headline mode included).
+                for every solver mode measured (the headline mode included);
+  sched_frac    steps/s times the bytes per step that the paper's two-sweep
+                schedule (Alg. 3 factorisation sweep, Alg. 4 substitution
+                sweeps, every sweep streaming its operands from memory; one
+                more pair of sweeps per refinement step, forward and adjoint)
+                would move, against the 8 TB/s peak: a fixed per-step
+                denominator that kernel fusion cannot inflate.
 """
 from __future__ import annotations
 
@@ -75,6 +81,20 @@ def kernel_bytes(rec, plan, io):
 
 
 # ------------------------------------------------------------- workload
+def sched_bytes_per_step(R, mode, refine):
+    """Bytes per solved step of the two-sweep schedule (block size k = R+1,
+    q = k(k+1)/2 packed factor entries): forward t-up sweep reads the inputs
+    (k+2) and writes L (q), P (k^2), alpha (k); t-down sweep reads P, alpha and
+    writes y; the adjoint reads g, P, L, writes alpha, then reads P, alpha, y,
+    the inputs and writes the gradients (k+2): 2q + 4k^2 + 10k + 6 elements.
+    Each refinement step adds, forward and adjoint, the residual's reads and
+    one more pair of substitution sweeps: 2q + 4k^2 + 13k + 4 elements."""
+    k = R + 1
+    q = k * (k + 1) // 2
+    elems = (2 * q + 4 * k * k + 10 * k + 6) + refine * (2 * q + 4 * k * k + 13 * k + 4)
+    return elems * (4 if mode == "fp32r" else 8)
+
+
 def make_workload(name, n_inst=None, T=None):
     from workloads import config
     return config(name, n_inst=n_inst, T=T)
@@ -335,11 +355,15 @@ def main():
         "roofline": roofline(head),
         "step_hbm_bytes_algorithmic": int(head["step_bytes"]),
         "step_bandwidth_frac": round(head["step_bytes"] / (head["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "sched_bytes_per_step": sched_bytes_per_step(bt.R, args.mode, head["refine"]),
+        "sched_frac": round(value * sched_bytes_per_step(bt.R, args.mode, head["refine"]) / 1e9 / HBM_PEAK_GBS, 4),
         "modes": {m: {"steps_per_s": round(bt.total_steps / (r["ms"] * 1e-3), 1), "ms_per_step": round(r["ms"], 5),
                       "err_vs_fp64_oracle": r["err"], "refine_steps": r["refine"], "chunk": r["chunk"],
                       "roofline_frac": roofline(r)["frac"], "eager_ms_per_step": round(r["ms_eager"], 5),
                       "timing": "hipGraph replay" if r["graph"] else "eager launches",
                       "step_bandwidth_frac": round(r["step_bytes"] / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                      "sched_frac": round(bt.total_steps / (r["ms"] * 1e-3) * sched_bytes_per_step(bt.R, m, r["refine"])
+                                          / 1e9 / HBM_PEAK_GBS, 4),
                       "traced_ms_per_step": round(r["ms_traced"], 5)}
                   for m, r in results.items()},
         "kernels": {k: {"avg_ms": round(v["ms"] / v["n"], 5), "launches": v["n"],
