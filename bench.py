@@ -290,6 +290,25 @@ def cpu_baseline(bt, target_s=15.0):
                       "gradients, %.1f s" % (n, bt.n_inst, int(bt.T[0]), reps, dt)}
 
 
+def lorenz_step_times():
+    """One JSON line: ms per optimisation step (window upload, solve forward,
+    loss, adjoint backward, Adam on a1..a7) of paper_2410_06074_amd.lorenz."""
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    from paper_2410_06074_amd.lorenz import step_time
+    rows = []
+    for B, T in ((512, 50), (512, 5), (512, 500), (64, 50), (4096, 50)):
+        ms = step_time(B, T)
+        log("lorenz B=%d T=%d: %.3f ms/step" % (B, T, ms))
+        rows.append({"batch": B, "seq_len": T, "ms_per_step": round(ms, 4)})
+    print(json.dumps({"metric": "Lorenz discovery optimisation step (Alg. 5), fp64r, R=2", "unit": "ms",
+                      "higher_is_better": False, "data": "synthetic (RK4 Lorenz trajectory)", "rows": rows}),
+          flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -307,9 +326,14 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: library default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--lorenz", action="store_true",
+                    help="only time the Lorenz discovery training step (Alg. 5) on the batch / window grid of "
+                         "the paper's Lorenz performance table")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration()
+    if args.lorenz:
+        return lorenz_step_times()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solve is per-instance independent and this build has no "
               "multi-GPU path (see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
