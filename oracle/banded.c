@@ -74,7 +74,7 @@ static void smooth_rows(int k, double s, double ws, double out[2 * KMAX][2 * KMA
 }
 
 /* Factor: Rd[t] (k x k upper), Ro[t] (k x k, coupling y_t -> y_{t+1}), z[t] (k). */
-static void factor(int R, int n_init, int64_t T, const double* c, const double* d, const double* s,
+static void factor(int R, int n_init, int t_init, int64_t T, const double* c, const double* d, const double* s,
                    const double* u0, const double* w, double* Rd, double* Ro, double* z) {
   const int k = R + 1;
   double carry[KMAX][KMAX + 1];
@@ -94,8 +94,8 @@ static void factor(int R, int n_init, int64_t T, const double* c, const double* 
     for (int j = 0; j < k; ++j) a[nrow][j] = w[0] * c[t * k + j];   /* Eq. 4 */
     a[nrow][rhs] = w[0] * d[t];
     ++nrow;
-    if (t == 0) {                                                      /* Eq. 5 */
-      for (int r = 0; r < n_init; ++r) { a[nrow][r] = w[1]; a[nrow][rhs] = w[1] * u0[r]; ++nrow; }
+    if (t < t_init) {                                                  /* Eq. 5 */
+      for (int r = 0; r < n_init; ++r) { a[nrow][r] = w[1]; a[nrow][rhs] = w[1] * u0[t * n_init + r]; ++nrow; }
     }
     int ncol = k;
     if (t + 1 < T) {                                                   /* Eqs. 6-7 */
@@ -160,7 +160,7 @@ static void fwd_solve_T(int k, int64_t T, const double* Rd, const double* Ro, co
   }
 }
 
-static int solve_one(int R, int n_init, int64_t T, const double* c, const double* d, const double* s,
+static int solve_one(int R, int n_init, int t_init, int64_t T, const double* c, const double* d, const double* s,
                      const double* u0, const double* w, double* y, double* lam, const double* g,
                      double* dc, double* dd, double* ds, double* du0, double* dw) {
   const int k = R + 1;
@@ -168,7 +168,7 @@ static int solve_one(int R, int n_init, int64_t T, const double* c, const double
   double* Ro = (double*)malloc(sizeof(double) * T * k * k);
   double* z = (double*)malloc(sizeof(double) * T * k);
   if (!Rd || !Ro || !z) { free(Rd); free(Ro); free(z); return 1; }
-  factor(R, n_init, T, c, d, s, u0, w, Rd, Ro, z);
+  factor(R, n_init, t_init, T, c, d, s, u0, w, Rd, Ro, z);
   back_solve(k, T, Rd, Ro, z, y);
   if (g) {
     fwd_solve_T(k, T, Rd, Ro, g, z);     /* R^T z = g */
@@ -183,10 +183,12 @@ static int solve_one(int R, int n_init, int64_t T, const double* c, const double
       dw[0] += -2.0 * wg * e * f;
       ds[t] = 0.0;
     }
-    for (int r = 0; r < n_init; ++r) {    /* initial rows */
-      du0[r] = wi * wi * lam[r];
-      dw[1] += -2.0 * wi * (y[r] - u0[r]) * lam[r];
-    }
+    for (int t = 0; t < t_init; ++t)      /* initial rows (none past the last point) */
+      for (int r = 0; r < n_init; ++r) {
+        if (t >= T) { du0[t * n_init + r] = 0.0; continue; }
+        du0[t * n_init + r] = wi * wi * lam[t * k + r];
+        dw[1] += -2.0 * wi * (y[t * k + r] - u0[t * n_init + r]) * lam[t * k + r];
+      }
     for (int64_t t = 0; t + 1 < T; ++t) { /* smoothness rows */
       const double st = s[t];
       double sr[2 * KMAX][2 * KMAX], dsr[2 * KMAX][2 * KMAX];
@@ -218,22 +220,23 @@ static int solve_one(int R, int n_init, int64_t T, const double* c, const double
 }
 
 /* Batched entry points.  off[N+1] = row offsets (instance i owns rows
- * off[i]..off[i+1]-1 of c [.,k], d, s, y [.,k]).  u0 is [N][n_init], w [N][3].
- * Returns the number of instances that failed to allocate. */
-int oracle_solve(int R, int n_init, int64_t N, const int64_t* off, const double* c, const double* d,
+ * off[i]..off[i+1]-1 of c [.,k], d, s, y [.,k]).  u0 is [N][t_init][n_init]
+ * (initial values at the first t_init points), w [N][3].  Returns the number
+ * of instances that failed to allocate. */
+int oracle_solve(int R, int n_init, int t_init, int64_t N, const int64_t* off, const double* c, const double* d,
                  const double* s, const double* u0, const double* w, double* y) {
   const int k = R + 1;
   int fails = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : fails)
   for (int64_t i = 0; i < N; ++i) {
     const int64_t o = off[i], T = off[i + 1] - off[i];
-    fails += solve_one(R, n_init, T, c + o * k, d + o, s + o, u0 + i * n_init, w + 3 * i, y + o * k,
-                       NULL, NULL, NULL, NULL, NULL, NULL, NULL);
+    fails += solve_one(R, n_init, t_init, T, c + o * k, d + o, s + o, u0 + i * t_init * n_init, w + 3 * i,
+                       y + o * k, NULL, NULL, NULL, NULL, NULL, NULL, NULL);
   }
   return fails;
 }
 
-int oracle_grad(int R, int n_init, int64_t N, const int64_t* off, const double* c, const double* d,
+int oracle_grad(int R, int n_init, int t_init, int64_t N, const int64_t* off, const double* c, const double* d,
                 const double* s, const double* u0, const double* w, const double* g, double* y,
                 double* lam, double* dc, double* dd, double* ds, double* du0, double* dw) {
   const int k = R + 1;
@@ -241,8 +244,9 @@ int oracle_grad(int R, int n_init, int64_t N, const int64_t* off, const double* 
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : fails)
   for (int64_t i = 0; i < N; ++i) {
     const int64_t o = off[i], T = off[i + 1] - off[i];
-    fails += solve_one(R, n_init, T, c + o * k, d + o, s + o, u0 + i * n_init, w + 3 * i, y + o * k,
-                       lam + o * k, g + o * k, dc + o * k, dd + o, ds + o, du0 + i * n_init, dw + 3 * i);
+    fails += solve_one(R, n_init, t_init, T, c + o * k, d + o, s + o, u0 + i * t_init * n_init, w + 3 * i,
+                       y + o * k, lam + o * k, g + o * k, dc + o * k, dd + o, ds + o, du0 + i * t_init * n_init,
+                       dw + 3 * i);
   }
   return fails;
 }
@@ -277,7 +281,7 @@ static double normalize(int64_t n, double* v) {
   return s;
 }
 
-static double cond_one(int R, int n_init, int64_t T, const double* c, const double* d, const double* s,
+static double cond_one(int R, int n_init, int t_init, int64_t T, const double* c, const double* d, const double* s,
                        const double* u0, const double* w, int iters) {
   const int k = R + 1;
   const int64_t n = T * k;
@@ -289,7 +293,7 @@ static double cond_one(int R, int n_init, int64_t T, const double* c, const doub
   double* t2 = (double*)malloc(sizeof(double) * n);
   double kappa = -1.0;
   if (Rd && Ro && z && v && t1 && t2) {
-    factor(R, n_init, T, c, d, s, u0, w, Rd, Ro, z);
+    factor(R, n_init, t_init, T, c, d, s, u0, w, Rd, Ro, z);
     double lmax = 0.0, lmin_inv = 0.0;
     for (int64_t i = 0; i < n; ++i) v[i] = 1.0 + 0.5 * sin(0.7 * (double)i);
     normalize(n, v);
@@ -312,14 +316,15 @@ static double cond_one(int R, int n_init, int64_t T, const double* c, const doub
   return kappa;
 }
 
-int oracle_cond(int R, int n_init, int64_t N, const int64_t* off, const double* c, const double* d,
+int oracle_cond(int R, int n_init, int t_init, int64_t N, const int64_t* off, const double* c, const double* d,
                 const double* s, const double* u0, const double* w, int iters, double* kappa) {
   const int k = R + 1;
   int fails = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : fails)
   for (int64_t i = 0; i < N; ++i) {
     const int64_t o = off[i], T = off[i + 1] - off[i];
-    kappa[i] = cond_one(R, n_init, T, c + o * k, d + o, s + o, u0 + i * n_init, w + 3 * i, iters);
+    kappa[i] = cond_one(R, n_init, t_init, T, c + o * k, d + o, s + o, u0 + i * t_init * n_init, w + 3 * i,
+                        iters);
     fails += kappa[i] < 0;
   }
   return fails;

@@ -5,9 +5,11 @@ this module.  Everything is float64 NumPy (plus torch float64 on the CPU for
 the autograd pin); sizes are limited by the dense m x n matrix (T up to ~1500
 for R = 2).
 
-One instance = one (batch, variable) pair, i.e. V = Q = 1 and T_init = 1 in
-the paper's notation; ``n_init`` = R_init + 1 initial orders are fixed at the
-first time point.
+One instance = one (batch, variable) pair, i.e. V = Q = 1 in the paper's
+notation.  ``u0`` holds the initial values of Eq. 5: a vector of n_init =
+R_init + 1 values fixes orders 0..R_init at the first time point (T_init = 1);
+a [T_init, n_init] array fixes them at each of the first T_init points (points
+past the instance's last one are ignored, and their gradients are zero).
 
 Functions and what pins them (tests/test_oracle_dense.py):
   weighted_system   App. A.1 (A, b, W) built row by row from Eqs. 4-7 and the
@@ -37,11 +39,18 @@ import numpy as np
 import scipy.linalg
 
 
-def constraint_counts(T: int, R: int, n_init: int):
-    """Eq. 8 with V = Q = 1, T_init = 1, R_init + 1 = n_init: (m, n)."""
-    m = T + n_init + 2 * (T - 1) * (R + 1)
+def constraint_counts(T: int, R: int, n_init: int, t_init: int = 1):
+    """Eq. 8 with V = Q = 1, R_init + 1 = n_init and T_init = t_init (capped
+    at T): (m, n)."""
+    m = T + min(t_init, T) * n_init + 2 * (T - 1) * (R + 1)
     n = T * (R + 1)
     return m, n
+
+
+def init_values(u0):
+    """u0 as a [T_init, n_init] array (a vector is one initial point)."""
+    u = np.asarray(u0, dtype=np.float64)
+    return u.reshape(1, -1) if u.ndim <= 1 else u
 
 
 def weighted_system(c, d, s, u0, w):
@@ -50,7 +59,8 @@ def weighted_system(c, d, s, u0, w):
     c  [T, R+1]  governing coefficients c_{t,r}      (Eq. 4)
     d  [T]       governing right-hand side d_t        (Eq. 4)
     s  [T]       s_t = step between points t and t+1; s[T-1] unused (Eqs. 6-7)
-    u0 [n_init]  initial values u_{1,r}, r < n_init   (Eq. 5)
+    u0 [n_init] or [T_init, n_init]  initial values u_{t,r}, t < T_init,
+                 r < n_init                           (Eq. 5)
     w  [3]       (w_gov, w_init, w_smooth), unsquared (weighting before Eq. 9)
 
     Rows are ordered [governing; initial; forward smoothness; backward
@@ -60,8 +70,9 @@ def weighted_system(c, d, s, u0, w):
     c = np.asarray(c, dtype=np.float64)
     T, k = c.shape
     R = k - 1
-    n_init = len(u0)
-    m, n = constraint_counts(T, R, n_init)
+    U = init_values(u0)
+    t_init, n_init = U.shape
+    m, n = constraint_counts(T, R, n_init, t_init)
     A = np.zeros((m, n))
     b = np.zeros(m)
     wd = np.zeros(m)
@@ -72,12 +83,13 @@ def weighted_system(c, d, s, u0, w):
         b[row] = d[t]
         wd[row] = w[0] ** 2
         row += 1
-    # initial values, Eq. 5: y_{1,r} = u_{1,r} for r <= R_init
-    for r in range(n_init):
-        A[row, r] = 1.0
-        b[row] = u0[r]
-        wd[row] = w[1] ** 2
-        row += 1
+    # initial values, Eq. 5: y_{t,r} = u_{t,r} for t <= T_init, r <= R_init
+    for t in range(min(t_init, T)):
+        for r in range(n_init):
+            A[row, t * k + r] = 1.0
+            b[row] = U[t, r]
+            wd[row] = w[1] ** 2
+            row += 1
     # forward smoothness, Eq. 6: y_{t+1,r} = sum_{r'>=r} s_t^{r'-r}/(r'-r)! y_{t,r'}
     for t in range(T - 1):
         for r in range(k):
@@ -120,20 +132,23 @@ def normal_matrix(c, d, s, u0, w):
 
 
 def normal_blocks_appendix(c, d, s, u0, w):
-    """App. A.2 written out for V = Q = 1, T_init = 1, R_init = n_init - 1.
+    """App. A.2 written out for V = Q = 1, R_init = n_init - 1 and any T_init.
 
     Returns (Mb [T,k,k], Nb [T-1,k,k], beta [T,k]) where Nb[t] is the block in
     block-row t+1, block-column t of M (Eq. 10)."""
     c = np.asarray(c, dtype=np.float64)
     T, k = c.shape
     R = k - 1
-    n_init = len(u0)
+    Uv = init_values(u0)
+    t_init, n_init = Uv.shape
     F = np.zeros((k, k))
     for i in range(k):
         for j in range(i, k):
             F[i, j] = 1.0 / math.factorial(j - i)
     U = np.diag([1.0 if r < n_init else 0.0 for r in range(k)])
-    uvec = np.array([u0[r] if r < n_init else 0.0 for r in range(k)])
+
+    def uvec(t):
+        return np.array([Uv[t, r] if r < n_init else 0.0 for r in range(k)])
 
     def Sp(t):
         return np.diag([s[t] ** r for r in range(k)])
@@ -163,8 +178,8 @@ def normal_blocks_appendix(c, d, s, u0, w):
     beta = np.zeros((T, k))
     for t in range(T):
         Ct = c[t][None, :]
-        Ut = U if t == 0 else np.zeros((k, k))
-        ut = uvec if t == 0 else np.zeros(k)
+        Ut = U if t < t_init else np.zeros((k, k))
+        ut = uvec(t) if t < t_init else np.zeros(k)
         Mb[t] = wg2 * Ct.T @ Ct + wi2 * Ut + ws2 * Sstar(t)
         beta[t] = wg2 * Ct.T[:, 0] * d[t] + wi2 * ut
     for t in range(T - 1):
@@ -189,17 +204,18 @@ def grad_rows(c, d, s, u0, w, y, lam):
     entering that row,
         dl/dtheta = -[ (da~/dtheta . lam) rho + mu (da~/dtheta . y - db~/dtheta) ].
     Summed over the rows that contain each parameter.  Returns a dict with
-    dc [T,k], dd [T], ds [T] (ds[T-1] = 0), du0 [n_init], dw [3]."""
+    dc [T,k], dd [T], ds [T] (ds[T-1] = 0), du0 (the shape of u0), dw [3]."""
     c = np.asarray(c, dtype=np.float64)
     T, k = c.shape
-    n_init = len(u0)
+    U = init_values(u0)
+    t_init, n_init = U.shape
     y = np.asarray(y).reshape(T, k)
     lam = np.asarray(lam).reshape(T, k)
     wg, wi, ws = (float(v) for v in w)
     dc = np.zeros((T, k))
     dd = np.zeros(T)
     ds = np.zeros(T)
-    du0 = np.zeros(n_init)
+    du0 = np.zeros((t_init, n_init))
     dw = np.zeros(3)
     # governing rows: a~ = wg c_t, b~ = wg d_t
     for t in range(T):
@@ -208,10 +224,11 @@ def grad_rows(c, d, s, u0, w, y, lam):
         dc[t] = -wg * wg * (e * lam[t] + f * y[t])
         dd[t] = wg * wg * f
         dw[0] += -2.0 * wg * e * f
-    # initial rows: a~ = wi e_r, b~ = wi u0_r
-    for r in range(n_init):
-        du0[r] = wi * wi * lam[0, r]
-        dw[1] += -2.0 * wi * (y[0, r] - u0[r]) * lam[0, r]
+    # initial rows: a~ = wi e_{t,r}, b~ = wi u_{t,r}
+    for t in range(min(t_init, T)):
+        for r in range(n_init):
+            du0[t, r] = wi * wi * lam[t, r]
+            dw[1] += -2.0 * wi * (y[t, r] - U[t, r]) * lam[t, r]
     # smoothness rows between t and t+1 (weighted by w_s s^r)
     for t in range(T - 1):
         st = s[t]
@@ -242,7 +259,7 @@ def grad_rows(c, d, s, u0, w, y, lam):
                 dy = da_t @ y[t] + da_n @ y[t + 1]
                 ds[t] += -(dlam * rho + mu * dy)
                 dw[2] += -2.0 * rho * mu / ws
-    return {"dc": dc, "dd": dd, "ds": ds, "du0": du0, "dw": dw}
+    return {"dc": dc, "dd": dd, "ds": ds, "du0": du0.reshape(np.shape(u0)), "dw": dw}
 
 
 def grad(c, d, s, u0, w, gy):
@@ -260,11 +277,11 @@ def grad_autograd(c, d, s, u0, w, gy):
     import torch
 
     T, k = np.shape(c)
-    n_init = len(u0)
+    t_init, n_init = init_values(u0).shape
     tc = torch.tensor(np.asarray(c, dtype=np.float64), requires_grad=True)
     td = torch.tensor(np.asarray(d, dtype=np.float64), requires_grad=True)
     ts = torch.tensor(np.asarray(s, dtype=np.float64), requires_grad=True)
-    tu = torch.tensor(np.asarray(u0, dtype=np.float64), requires_grad=True)
+    tu = torch.tensor(init_values(u0), requires_grad=True)
     tw = torch.tensor(np.asarray(w, dtype=np.float64), requires_grad=True)
     rows_a, rows_b, rows_w = [], [], []
     zero = torch.zeros((), dtype=torch.float64)
@@ -272,10 +289,11 @@ def grad_autograd(c, d, s, u0, w, gy):
         a = torch.zeros(T * k, dtype=torch.float64)
         a = a.index_put((torch.arange(t * k, (t + 1) * k),), tc[t])
         rows_a.append(a); rows_b.append(td[t]); rows_w.append(tw[0])
-    for r in range(n_init):
-        a = torch.zeros(T * k, dtype=torch.float64)
-        a[r] = 1.0
-        rows_a.append(a); rows_b.append(tu[r]); rows_w.append(tw[1])
+    for t in range(min(t_init, T)):
+        for r in range(n_init):
+            a = torch.zeros(T * k, dtype=torch.float64)
+            a[t * k + r] = 1.0
+            rows_a.append(a); rows_b.append(tu[t, r]); rows_w.append(tw[1])
     for direction in (+1, -1):
         for t in range(T - 1):
             for r in range(k):
@@ -298,4 +316,4 @@ def grad_autograd(c, d, s, u0, w, gy):
     loss = (torch.as_tensor(np.asarray(gy, dtype=np.float64).reshape(-1)) * y).sum()
     loss.backward()
     return {"y": y.detach().numpy().reshape(T, k), "dc": tc.grad.numpy(), "dd": td.grad.numpy(),
-            "ds": ts.grad.numpy(), "du0": tu.grad.numpy(), "dw": tw.grad.numpy()}
+            "ds": ts.grad.numpy(), "du0": tu.grad.numpy().reshape(np.shape(u0)), "dw": tw.grad.numpy()}

@@ -121,3 +121,26 @@ def test_condition_estimate_matches_dense_svd():
         M, _ = D.normal_matrix(c, d, s, u0, w)
         ref = np.linalg.cond(M)
         assert abs(kap[i] - ref) <= 0.05 * ref
+
+
+@pytest.mark.parametrize("t_init,n_init", [(2, 2), (5, 1), (40, 3)])
+def test_banded_matches_dense_with_several_initial_points(t_init, n_init):
+    # ragged lengths below, at and above T_init; points past an instance's end
+    # carry no initial row and get a zero gradient
+    bt = gaussian_batch(4, [1, 3, 5, 30], R=2, seed=60 + t_init, n_init=n_init, weights=(1.2, 0.8, 1.5),
+                        t_init=t_init)
+    gy = np.random.default_rng(t_init).standard_normal(bt.c.shape)
+    gb = banded.grad(bt, gy)
+    o = bt.offsets
+    for i in range(bt.n_inst):
+        c, d, s, u0, w = bt.instance(i)
+        if bt.T[i] * bt.k > bt.T[i] + min(t_init, bt.T[i]) * n_init + 2 * (bt.T[i] - 1) * bt.k:
+            continue   # fewer rows than unknowns: not solvable
+        gd = dense.grad(c, d, s, u0, w, gy[o[i]:o[i + 1]])
+        M, _ = dense.normal_matrix(c, d, s, u0, w)
+        tol = max(1e-10, 100 * np.linalg.cond(M) * np.finfo(float).eps)
+        assert _rel(gb["y"][o[i]:o[i + 1]], gd["y"]) < tol
+        for key in ("lam", "dc", "dd", "ds"):
+            assert _rel(gb[key][o[i]:o[i + 1]], gd[key]) < tol, key
+        assert _rel(gb["du0"][i], gd["du0"].ravel()) < tol
+        assert np.all(gb["du0"][i].reshape(t_init, n_init)[bt.T[i]:] == 0.0)

@@ -16,8 +16,8 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _inst(T, R, seed, n_init=None, weights=(1.0, 1.0, 1.0)):
-    bt = gaussian_batch(1, T, R=R, seed=seed, n_init=n_init, weights=weights)
+def _inst(T, R, seed, n_init=None, weights=(1.0, 1.0, 1.0), t_init=1):
+    bt = gaussian_batch(1, T, R=R, seed=seed, n_init=n_init, weights=weights, t_init=t_init)
     return bt.instance(0)
 
 
@@ -256,3 +256,71 @@ def test_planted_missing_smoothness_weight_is_caught():
     M_bad = A.T @ (wd_bad[:, None] * A)
     Mb, _, _ = dense.normal_blocks_appendix(c, d, s, u0, w)
     assert np.abs(M_bad[:k, :k] - Mb[0]).max() > 1e-3   # the App. A.2 identity pin fails
+
+
+# ------------------------------------------- initial values at T_init points
+@pytest.mark.parametrize("T,R,n_init,t_init", [(6, 2, 2, 3), (4, 1, 1, 4), (3, 3, 4, 5), (9, 2, 3, 2)])
+def test_row_counts_match_eq8_with_several_initial_points(T, R, n_init, t_init):
+    c, d, s, u0, w = _inst(T, R, 1, n_init=n_init, t_init=t_init, weights=(1.0, 2.0, 0.5))
+    A, b, wd = dense.weighted_system(c, d, s, u0, w)
+    # Eq. 8: T_init V (R_init + 1) initial rows; points past T carry none
+    assert A.shape == (T + min(t_init, T) * n_init + 2 * (T - 1) * (R + 1), T * (R + 1))
+    init = np.flatnonzero(wd == 4.0)
+    assert len(init) == min(t_init, T) * n_init
+    for j, row in enumerate(init):   # row j fixes order j % n_init at point j // n_init
+        t, r = divmod(j, n_init)
+        assert np.flatnonzero(A[row]).tolist() == [t * (R + 1) + r] and b[row] == u0[t, r]
+
+
+@pytest.mark.parametrize("T,R,n_init,t_init,weights", [(6, 2, 2, 3, (1.5, 0.3, 0.8)), (5, 3, 1, 5, (0.2, 4.0, 1.7)),
+                                                       (3, 1, 2, 4, (1.0, 2.0, 1.0))])
+def test_appendix_blocks_with_several_initial_points(T, R, n_init, t_init, weights):
+    # App. A.2: U_t and u_t are non-zero for t <= T_init; the dense A^T W A
+    # built from the rows of Eq. 5 must agree block by block
+    c, d, s, u0, w = _inst(T, R, 8, n_init=n_init, weights=weights, t_init=t_init)
+    M, beta = dense.normal_matrix(c, d, s, u0, w)
+    Mb, Nb, bb = dense.normal_blocks_appendix(c, d, s, u0, w)
+    k = R + 1
+    scale = np.abs(M).max()
+    for t in range(T):
+        assert np.abs(M[t * k:(t + 1) * k, t * k:(t + 1) * k] - Mb[t]).max() <= 1e-14 * scale
+        if t + 1 < T:
+            assert np.abs(M[(t + 1) * k:(t + 2) * k, t * k:(t + 1) * k] - Nb[t]).max() <= 1e-14 * scale
+    assert np.abs(beta.reshape(T, k) - bb).max() <= 1e-14 * max(1.0, np.abs(beta).max())
+
+
+def test_every_unknown_fixed_by_initial_rows_returns_them():
+    # T_init = T and R_init = R with only the initial rows weighted: M = w_i^2 I,
+    # so y = u exactly
+    T, R = 7, 2
+    c, d, s, u0, w = _inst(T, R, 4, n_init=R + 1, t_init=T, weights=(0.0, 1.7, 0.0))
+    y = dense.solve(c, d, s, u0, w)
+    assert np.abs(y - u0).max() <= 1e-14 * np.abs(u0).max()
+
+
+def test_gradients_with_several_initial_points_match_autograd_and_fd():
+    R, T, t_init = 2, 8, 3
+    c, d, s, u0, w = _inst(T, R, 31, n_init=2, t_init=t_init, weights=(1.2, 0.9, 1.4))
+    assert u0.shape == (t_init, 2)
+    gy = np.random.default_rng(4).standard_normal((T, R + 1))
+    ours = dense.grad(c, d, s, u0, w, gy)
+    ref = dense.grad_autograd(c, d, s, u0, w, gy)
+    M, _ = dense.normal_matrix(c, d, s, u0, w)
+    tol = max(1e-9, 100 * np.linalg.cond(M) * np.finfo(float).eps)
+    for key in ("dc", "dd", "ds", "du0"):
+        assert _rel(ours[key], ref[key]) < tol, key
+    scale = np.linalg.norm(ref["dc"])
+    assert np.linalg.norm(ours["dw"] - ref["dw"]) <= tol * max(np.linalg.norm(ref["dw"]), scale)
+    # du at a later initial point, and the initial weight, by central differences
+    for (t, r) in ((2, 1), (1, 0)):
+        h = 1e-5
+        up, um = u0.copy(), u0.copy()
+        up[t, r] += h
+        um[t, r] -= h
+        fd = (np.sum(gy * dense.solve(c, d, s, up, w)) - np.sum(gy * dense.solve(c, d, s, um, w))) / (2 * h)
+        assert abs(fd - ours["du0"][t, r]) <= 1e-6 * max(1.0, abs(fd))
+    wp, wm = w.copy(), w.copy()
+    wp[1] += 1e-5
+    wm[1] -= 1e-5
+    fd = (np.sum(gy * dense.solve(c, d, s, u0, wp)) - np.sum(gy * dense.solve(c, d, s, u0, wm))) / 2e-5
+    assert abs(fd - ours["dw"][1]) <= 1e-6 * max(1.0, abs(fd))

@@ -9,7 +9,8 @@ Layout (the "natural" layout the C-ABI consumes, see ``include/smnn.h``):
 per-step arrays are instance-major and time-contiguous.  Instance ``i`` owns
 rows ``off[i] .. off[i] + T[i] - 1`` where ``off`` is the exclusive prefix sum
 of ``T``.  ``c`` is ``[S, R+1]``, ``b`` and ``h`` are ``[S]``, ``u0`` is
-``[N, n_init]``, ``w`` is ``[N, 3]`` (unsquared governing / initial /
+``[N, t_init * n_init]`` (initial values of orders ``0..n_init-1`` at each of
+the first ``t_init`` time points, point-major), ``w`` is ``[N, 3]`` (unsquared governing / initial /
 smoothness weights), with ``S = sum(T)``.  ``h[off[i] + t]`` is the step size
 between time points ``t`` and ``t+1``; the last slot of each instance is not
 used by the solve (it is drawn anyway so every slot holds a finite value).
@@ -37,6 +38,7 @@ class Batch:
     u0: np.ndarray         # [N, n_init]
     w: np.ndarray          # [N, 3]
     name: str = ""
+    t_init: int = 1        # time points carrying initial values
 
     @property
     def n_inst(self) -> int:
@@ -57,13 +59,15 @@ class Batch:
         return int(self.T.sum())
 
     def instance(self, i: int):
-        """(c, b, h, u0, w) of instance i as float64 views/copies."""
+        """(c, b, h, u0, w) of instance i as float64 views/copies; u0 is
+        [n_init] when t_init = 1, else [t_init, n_init]."""
         o = self.offsets
         s, e = int(o[i]), int(o[i + 1])
         return (np.asarray(self.c[s:e], dtype=np.float64),
                 np.asarray(self.b[s:e], dtype=np.float64),
                 np.asarray(self.h[s:e], dtype=np.float64),
-                np.asarray(self.u0[i], dtype=np.float64),
+                (np.asarray(self.u0[i], dtype=np.float64) if self.t_init == 1
+                 else np.asarray(self.u0[i], dtype=np.float64).reshape(self.t_init, self.n_init)),
                 np.asarray(self.w[i], dtype=np.float64))
 
     def astype(self, dtype) -> "Batch":
@@ -79,7 +83,7 @@ class Batch:
         return Batch(R=self.R, n_init=self.n_init, T=self.T[list(idx)].copy(),
                      c=self.c[rows].copy(), b=self.b[rows].copy(), h=self.h[rows].copy(),
                      u0=self.u0[list(idx)].copy(), w=self.w[list(idx)].copy(),
-                     name=self.name + "[subset]")
+                     name=self.name + "[subset]", t_init=self.t_init)
 
 
 def _gaussian_c(rng, S, R, scale=1.0):
@@ -100,9 +104,10 @@ def _ar1(rng, n_series: int, T: int, rho: float) -> np.ndarray:
 
 
 def gaussian_batch(n_inst: int, T, R: int = 2, seed: int = 0, n_init: int | None = None,
-                   weights=(1.0, 1.0, 1.0), h0: float = 0.01, name: str = "") -> Batch:
+                   weights=(1.0, 1.0, 1.0), h0: float = 0.01, name: str = "", t_init: int = 1) -> Batch:
     """c_{t,r<R} ~ N(0,1), c_{t,R} = 1+|N(0,1)|, b ~ N(0,1), h = h0*(0.5+U[0,1)),
-    u0 ~ N(0,1), constant weights.  ``T`` is an int (uniform) or an array."""
+    u0 ~ N(0,1) at t_init points, constant weights.  ``T`` is an int (uniform)
+    or an array."""
     rng = np.random.default_rng(seed)
     Ts = np.full(n_inst, int(T), dtype=np.int64) if np.isscalar(T) else np.asarray(T, dtype=np.int64)
     S = int(Ts.sum())
@@ -110,9 +115,9 @@ def gaussian_batch(n_inst: int, T, R: int = 2, seed: int = 0, n_init: int | None
     c = _gaussian_c(rng, S, R)
     b = rng.standard_normal(S)
     h = h0 * (0.5 + rng.random(S))
-    u0 = rng.standard_normal((n_inst, n_init))
+    u0 = rng.standard_normal((n_inst, t_init * n_init))
     w = np.tile(np.asarray(weights, dtype=np.float64), (n_inst, 1))
-    return Batch(R=R, n_init=n_init, T=Ts, c=c, b=b, h=h, u0=u0, w=w, name=name)
+    return Batch(R=R, n_init=n_init, T=Ts, c=c, b=b, h=h, u0=u0, w=w, name=name, t_init=t_init)
 
 
 def config(name: str, seed: int | None = None, n_inst: int | None = None, T: int | None = None) -> Batch:
