@@ -7,7 +7,9 @@
  * y_{t,r}, r = 0..R (the r-th derivative at point t).  Its weighted
  * constraints are
  *   governing (Eq. 4):   sum_r c_{t,r} y_{t,r} = b_t                 weight w_gov
- *   initial   (Eq. 5):   y_{1,r} = u0_r, r < n_init (T_init = 1)      weight w_init
+ *   initial   (Eq. 5):   y_{t,r} = u0_{t,r}, t < T_init, r < n_init     weight w_init
+ *                        (T_init = init_points; points past an instance's
+ *                        last one carry no row)
  *   smoothness (Eqs. 6-7): forward and backward Taylor expansions between
  *                        points t and t+1 with step h_t, every order
  *                        r = 0..R, each row weighted by w_smooth * h_t^r
@@ -43,10 +45,11 @@
  *   b   [S]       governing right-hand side
  *   h   [S]       h[off[i]+t] = step between points t and t+1; the last slot
  *                 of each instance is read by nothing
- *   u0  [N][n_init]  initial values
+ *   u0  [N][T_init][n_init]  initial values (point-major per instance)
  *   w   [N][3]    (w_gov, w_init, w_smooth), unsquared, > 0
  *   y   [S][R+1]  solution; gy, dc share this shape; db, dh share b's;
- *                 du0 shares u0's; dw shares w's.
+ *                 du0 shares u0's (entries for points past an instance's
+ *                 end are written as 0); dw shares w's.
  * For a uniform batch these are contiguous (N, T, R+1), (N, T), ... arrays.
  *
  * Ownership.  The caller allocates and owns every buffer.  `factor`
@@ -95,7 +98,7 @@ typedef struct smnn_plan smnn_plan; /* opaque; immutable after creation */
 
 typedef struct {
   int32_t order;          /* R, 1..4 (block size R+1) */
-  int32_t n_init;         /* initial orders fixed at the first point, 0..R+1 */
+  int32_t n_init;         /* initial orders fixed at each initial point, 0..R+1 */
   int64_t n_inst;         /* N >= 1 */
   const int64_t* steps;   /* HOST array [N] of T_i >= 1, or NULL: all T_i = steps_uniform */
   int64_t steps_uniform;
@@ -106,6 +109,7 @@ typedef struct {
   int32_t block;          /* threads per workgroup (64..256, multiple of 64); 0: 64 */
   int32_t max_blocks;     /* >0: persistent grid-stride launch with at most this many
                              workgroups per kernel; 0: one wavefront per tile */
+  int32_t init_points;    /* T_init: leading time points with initial values (Eq. 5); 0: 1 */
 } smnn_plan_desc;
 
 /* Create a plan on the current HIP device: validates the description,
@@ -122,12 +126,14 @@ smnn_status smnn_plan_sizes(const smnn_plan* plan, size_t* factor_bytes, size_t*
                             int64_t* total_steps);
 
 /* Introspection: SMNN_Q_LEVELS, SMNN_Q_CHUNK, SMNN_Q_CHUNK_UPPER, SMNN_Q_NODES(l),
- * SMNN_Q_CHUNKS(l), SMNN_Q_REFINE, SMNN_Q_MODE.  Returns -1 for an unknown key. */
+ * SMNN_Q_CHUNKS(l), SMNN_Q_REFINE, SMNN_Q_MODE, SMNN_Q_INIT_POINTS.  Returns -1 for an
+ * unknown key. */
 #define SMNN_Q_LEVELS 1
 #define SMNN_Q_CHUNK 2
 #define SMNN_Q_REFINE 3
 #define SMNN_Q_MODE 4
 #define SMNN_Q_CHUNK_UPPER 5
+#define SMNN_Q_INIT_POINTS 6
 #define SMNN_Q_NODES(l) (1000 + (l))
 #define SMNN_Q_CHUNKS(l) (2000 + (l))
 int64_t smnn_plan_query(const smnn_plan* plan, int32_t key);

@@ -15,6 +15,7 @@ using namespace smnn;
 
 struct smnn_plan {
   int R = 0, K = 0, n_init = 0, mode = 0, refine = 0, L0 = 8, L1 = 8;
+  int t_init = 1;   // time points carrying initial values
   int64_t N = 0, S = 0;
   int device = 0;
   bool f32 = false;
@@ -169,6 +170,7 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   if (!d) return SMNN_ERR_INVALID_ARG;
   if (d->order < 1 || d->order > 4) return SMNN_ERR_INVALID_ARG;
   if (d->n_init < 0 || d->n_init > d->order + 1) return SMNN_ERR_INVALID_ARG;
+  if (d->init_points < 0 || d->init_points > (1 << 30)) return SMNN_ERR_INVALID_ARG;
   if (d->n_inst < 1 || d->n_inst > INT32_MAX) return SMNN_ERR_INVALID_ARG;
   if (d->mode < SMNN_MODE_FP64 || d->mode > SMNN_MODE_FP32_REFINED) return SMNN_ERR_INVALID_ARG;
   if (d->refine_steps < -1 || d->refine_steps > 2) return SMNN_ERR_INVALID_ARG;
@@ -191,6 +193,7 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   p->R = d->order;
   p->K = K;
   p->n_init = d->n_init;
+  p->t_init = d->init_points > 0 ? d->init_points : 1;
   p->mode = d->mode;
   p->refine = d->mode == SMNN_MODE_FP64 ? 0 : (d->refine_steps < 0 ? 1 : d->refine_steps);
   p->L0 = L0;
@@ -355,6 +358,7 @@ int64_t smnn_plan_query(const smnn_plan* p, int32_t key) {
   if (key == SMNN_Q_CHUNK_UPPER) return p->L1;
   if (key == SMNN_Q_REFINE) return p->refine;
   if (key == SMNN_Q_MODE) return p->mode;
+  if (key == SMNN_Q_INIT_POINTS) return p->t_init;
   if (key >= 1000 && key < 1000 + static_cast<int32_t>(p->lev.size())) return p->lev[key - 1000].nodes;
   if (key >= 2000 && key < 2000 + static_cast<int32_t>(p->lev.size())) return p->lev[key - 2000].chunks;
   return -1;
@@ -375,6 +379,7 @@ smnn_status smnn_forward(const smnn_plan* p, const void* c, const void* b, const
   Level0Args a;
   a.c = c; a.d = b; a.s = h; a.u0 = u0; a.w = w;
   a.n_init = p->n_init;
+  a.t_init = p->t_init;
   a.L0 = p->L0;
   a.L1 = p->L1;
   a.N = p->N;
@@ -418,6 +423,7 @@ smnn_status smnn_backward(const smnn_plan* p, const void* c, const void* b, cons
   a.c = c; a.d = b; a.s = h; a.u0 = u0; a.w = w; a.g = gy; a.y = y;
   a.dc = dc; a.dd = db; a.ds = dh; a.du0 = du0; a.dw = dw; a.dw_part = bd.dwp;
   a.n_init = p->n_init;
+  a.t_init = p->t_init;
   a.L0 = p->L0;
   a.L1 = p->L1;
   a.N = p->N;
@@ -475,7 +481,7 @@ smnn_status time_candidate(const smnn_plan_desc& d, const void* c, const void* b
   if (hipMalloc(&y, io * S * K) != hipSuccess || hipMalloc(&fac, p->factor_bytes) != hipSuccess ||
       hipMalloc(&ws, p->workspace_bytes) != hipSuccess || hipMalloc(&dc, io * S * K) != hipSuccess ||
       hipMalloc(&db, io * S) != hipSuccess || hipMalloc(&dh, io * S) != hipSuccess ||
-      hipMalloc(&du0, io * (N * p->n_init + 1)) != hipSuccess || hipMalloc(&dw, io * N * 3) != hipSuccess ||
+      hipMalloc(&du0, io * (N * p->t_init * p->n_init + 1)) != hipSuccess || hipMalloc(&dw, io * N * 3) != hipSuccess ||
       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     cleanup();
     return SMNN_ERR_HIP;

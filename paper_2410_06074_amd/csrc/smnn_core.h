@@ -575,12 +575,14 @@ SMNN_HD int backsub_chunk(const Src& src, int64_t a, int64_t b, bool has_left, b
 }
 
 // ----------------------------------------------------------- level-0 source
-// Per-instance parameters: weights (unsquared) and initial values.
+// Per-instance parameters: weights (unsquared), and the shape of the
+// initial rows (Eq. 5): orders < n_init at each of the first t_init points.
+// The initial values themselves are read from memory at those nodes only.
 template <int K>
 struct Inst {
   double wg, wi, ws;
-  double u0[K];
   int n_init;
+  int t_init = 1;
 };
 
 enum RhsMode : int {
@@ -599,6 +601,8 @@ struct Src0 {
   const TIO* s;      // [..]  (s of the last node unused)
   const TIO* g;      // [..][K]  dl/dy (RHS_G, RHS_GRESID)
   const TIO* v;      // [..][K]  previous iterate (RHS_RESID, RHS_GRESID)
+  const TIO* u = nullptr;   // initial values of every instance, [N][t_init][n_init]
+  int uo = 0;               // element offset of this instance's block in u
   int64_t n;
   int64_t o = 0;     // row of node 0 in the arrays above
   Inst<K> p;
@@ -608,6 +612,10 @@ struct Src0 {
   mutable int64_t carry_node = -1;
 
   SMNN_HD double ld(const TIO* ptr, int64_t i) const { return static_cast<double>(ptr[o + i]); }
+  // initial value of order r at node i < t_init
+  SMNN_HD double uval(int64_t i, int r) const {
+    return static_cast<double>(u[uo + static_cast<int>(i) * p.n_init + r]);
+  }
   SMNN_HD double ldk(const TIO* ptr, int64_t i, int r) const { return static_cast<double>(ptr[(o + i) * K + r]); }
 
   SMNN_HD void coupling(int64_t i, double (&B)[Dim<K>::KK]) const {
@@ -633,10 +641,10 @@ struct Src0 {
     const double we = wg2 * e;
 #pragma unroll
     for (int r = 0; r < K; ++r) f[r] = (RHS == RHS_GRESID) ? fma(ci[r], we, ldk(g, i, r)) : ci[r] * we;
-    if (i == 0) {
+    if (i < p.t_init) {
 #pragma unroll
       for (int r = 0; r < K; ++r)
-        if (r < p.n_init) f[r] += wi2 * ((RHS == RHS_RESID ? p.u0[r] : 0.0) - vi[r]);
+        if (r < p.n_init) f[r] += wi2 * ((RHS == RHS_RESID ? uval(i, r) : 0.0) - vi[r]);
     }
     if (has_prev) {
       double cr[K];
@@ -672,7 +680,7 @@ struct Src0 {
     for (int r = 0; r < K; ++r)
 #pragma unroll
       for (int q = 0; q <= r; ++q) A[tri(r, q)] = wg2 * ci[r] * ci[q];
-    if (i == 0) {
+    if (i < p.t_init) {
 #pragma unroll
       for (int r = 0; r < K; ++r)
         if (r < p.n_init) A[tri(r, r)] += wi2;
@@ -692,10 +700,10 @@ struct Src0 {
       const double di = ld(d, i);
 #pragma unroll
       for (int r = 0; r < K; ++r) f[r] = wg2 * ci[r] * di;
-      if (i == 0) {
+      if (i < p.t_init) {
 #pragma unroll
         for (int r = 0; r < K; ++r)
-          if (r < p.n_init) f[r] += wi2 * p.u0[r];
+          if (r < p.n_init) f[r] += wi2 * uval(i, r);
       }
     } else if (RHS == RHS_G) {
 #pragma unroll
@@ -735,7 +743,9 @@ template <int K, class TIO, bool ADD>
 struct GradSink {
   const TIO *c, *d, *s, *y, *v;   // inputs: node i is row o + i
   TIO *dc, *dd, *ds;              // outputs: node i is row oo + i
-  TIO* du0;                       // this instance's [n_init]
+  TIO* du0;                       // this instance's [t_init][n_init]
+  const TIO* u = nullptr;         // initial values of every instance, [N][t_init][n_init]
+  int uo = 0;                     // element offset of this instance's block in u
   int64_t o = 0, oo = 0;
   Inst<K> p;
   double lam_n[K], y_n[K];   // node i+1 (the one finished before)
@@ -762,12 +772,13 @@ struct GradSink {
     for (int r = 0; r < K; ++r) dc[(oo + i) * K + r] = static_cast<TIO>(-wg2 * (e * lam[r] + f * yi[r]));
     dd[oo + i] = static_cast<TIO>(wg2 * f);
     dw[0] += -2.0 * p.wg * e * f;
-    if (i == 0) {
+    if (i < p.t_init) {
 #pragma unroll
       for (int r = 0; r < K; ++r)
         if (r < p.n_init) {
-          du0[r] = static_cast<TIO>(p.wi * p.wi * lam[r]);
-          dw[1] += -2.0 * p.wi * (yi[r] - p.u0[r]) * lam[r];
+          const double ur = static_cast<double>(u[uo + static_cast<int>(i) * p.n_init + r]);
+          du0[i * p.n_init + r] = static_cast<TIO>(p.wi * p.wi * lam[r]);
+          dw[1] += -2.0 * p.wi * (yi[r] - ur) * lam[r];
         }
     }
   }
@@ -795,6 +806,12 @@ struct GradSink {
 #pragma unroll
     for (int e = 0; e < K; ++e) { lam_n[e] = lam[e]; y_n[e] = yi[e]; }
     have_next = true;
+  }
+  // initial points past the instance's last node (n < t_init) have no row:
+  // their gradient is zero (called by the lane owning the instance's end)
+  SMNN_HD void zero_past_end(int64_t n) {
+    for (int64_t t = n; t < p.t_init; ++t)
+      for (int r = 0; r < p.n_init; ++r) du0[t * p.n_init + r] = static_cast<TIO>(0.0);
   }
   // the chunk's left separator: only the smoothness pair (i, i+1) is owned here
   SMNN_HD void left(int64_t i, const double (&x)[K]) {

@@ -25,7 +25,7 @@ struct Level0Args {
   const void* c = nullptr;   // [S][K]
   const void* d = nullptr;   // [S]
   const void* s = nullptr;   // [S]
-  const void* u0 = nullptr;  // [N][n_init]
+  const void* u0 = nullptr;  // [N][t_init][n_init]
   const void* w = nullptr;   // [N][3]
   const void* g = nullptr;   // [S][K]  dl/dy
   const void* v = nullptr;   // [S][K]  previous iterate (refinement passes)
@@ -34,11 +34,12 @@ struct Level0Args {
   void* dc = nullptr;        // [S][K]
   void* dd = nullptr;        // [S]
   void* ds = nullptr;        // [S]
-  void* du0 = nullptr;       // [N][n_init]
+  void* du0 = nullptr;       // [N][t_init][n_init]
   double* dw_part = nullptr; // [chunks0][3] per-chunk partial sums
   void* dw = nullptr;        // [N][3]
   uint32_t* info = nullptr;  // [N] smallest failing step + 1 (UINT32_MAX = none)
   int n_init = 0;
+  int t_init = 1;            // points carrying initial values
   int L0 = 8, L1 = 8;        // chunk lengths of level 0 and of levels >= 1
   int64_t N = 0;
   int wpb = 1;               // waves per workgroup of the launch (set by the launcher)

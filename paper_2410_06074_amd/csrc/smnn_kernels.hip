@@ -145,34 +145,13 @@ __device__ __forceinline__ void unstage_rows(void* dst, int w, int64_t r0, int64
 template <int K, class TIO>
 __device__ __forceinline__ Inst<K> load_inst(const Level0Args& a, int64_t i) {
   const TIO* w = static_cast<const TIO*>(a.w);
-  const TIO* u0 = static_cast<const TIO*>(a.u0);
   Inst<K> p;
   p.wg = static_cast<double>(w[3 * i]);
   p.wi = static_cast<double>(w[3 * i + 1]);
   p.ws = static_cast<double>(w[3 * i + 2]);
   p.n_init = a.n_init;
-  // unconditional loads (clamped to a valid element) so they issue together
-  const int ni = a.n_init;
-  const TIO* ub = ni > 0 ? u0 + i * ni : w + 3 * i;
-#pragma unroll
-  for (int r = 0; r < K; ++r) {
-    const double val = static_cast<double>(ub[ni > 0 ? (r < ni ? r : ni - 1) : 0]);
-    p.u0[r] = r < ni ? val : 0.0;
-  }
+  p.t_init = a.t_init;
   return p;
-}
-
-template <int K, class TIO, int RHS>
-__device__ __forceinline__ Src0<K, TIO, RHS> make_src0(const Level0Args& a, int64_t i, int64_t off, int64_t n) {
-  Src0<K, TIO, RHS> S;
-  S.c = static_cast<const TIO*>(a.c) + off * K;
-  S.d = static_cast<const TIO*>(a.d) + off;
-  S.s = static_cast<const TIO*>(a.s) + off;
-  S.g = a.g ? static_cast<const TIO*>(a.g) + off * K : nullptr;
-  S.v = a.v ? static_cast<const TIO*>(a.v) + off * K : nullptr;
-  S.n = n;
-  S.p = load_inst<K, TIO>(a, i);
-  return S;
 }
 
 // Source reading the wave's LDS slice: node i of the instance at global
@@ -187,6 +166,8 @@ __device__ __forceinline__ Src0<K, TIO, RHS> make_src0_lds(const Level0Args& a, 
   S.d = reinterpret_cast<const TIO*>(sl + ST::D);
   S.g = reinterpret_cast<const TIO*>(sl + ST::G);
   S.v = reinterpret_cast<const TIO*>(sl + ST::V);
+  S.u = static_cast<const TIO*>(a.u0);
+  S.uo = static_cast<int>(i) * a.t_init * a.n_init;
   S.o = off - lo;
   S.n = n;
   S.p = load_inst<K, TIO>(a, i);
@@ -423,12 +404,17 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub0(LevelDev l0, L
         sink.dd = reinterpret_cast<TIO*>(sl + ST::D);
         sink.ds = reinterpret_cast<TIO*>(sl + ST::S);
         sink.oo = off - lo;
-        sink.du0 = static_cast<TIO*>(a.du0) + inst * a.n_init;
+        sink.du0 = static_cast<TIO*>(a.du0) + inst * a.t_init * a.n_init;
+        sink.u = src.u;
+        sink.uo = src.uo;
         sink.p = src.p;
         if (geo.has_right) sink.start(geo.b + 1, xr);
         backsub_backward<K, L>(src, geo.a, geo.b, Ls, xs, sink);
         if (geo.has_left) sink.left(geo.a - 1, xl);
-        if (!geo.has_right) sink.ds[sink.oo + n - 1] = static_cast<TIO>(0.0);   // s of the last point is unused
+        if (!geo.has_right) {
+          sink.ds[sink.oo + n - 1] = static_cast<TIO>(0.0);   // s of the last point is unused
+          sink.zero_past_end(n);
+        }
 #pragma unroll
         for (int e = 0; e < 3; ++e) a.dw_part[g * 3 + e] = sink.dw[e];
         if (fail) report_fail(a, inst, 0, geo.a + fail - 1);
@@ -513,7 +499,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDe
     // 2. reduce with the residual of that iterate as right-hand side
     Src0<K, TIO, ROUT> rs;
     rs.c = src.c; rs.d = src.d; rs.s = src.s; rs.g = src.g; rs.v = it;
-    rs.n = src.n; rs.o = src.o; rs.p = src.p;
+    rs.n = src.n; rs.o = src.o; rs.p = src.p; rs.u = src.u; rs.uo = src.uo;
     Reduced<K> red;
 #pragma unroll
     for (int e = 0; e < Dim<K>::Q; ++e) { red.rA[e] = 0.0; red.lA[e] = 0.0; }

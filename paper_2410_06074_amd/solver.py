@@ -21,6 +21,8 @@ class Plan:
     """A solver plan: sizes, mode and the per-level partition of a batch.
 
     steps: int (every instance has that many steps) or a sequence of T_i.
+    init_points: T_init, the leading time points that carry the n_init
+           initial values (u0 is then N x T_init x n_init).
     mode:  'fp64' (the paper's single solve), 'fp64r' (plus row-residual
            refinement) or 'fp32r' (float32 memory traffic, float64 arithmetic,
            refinement).
@@ -28,7 +30,7 @@ class Plan:
 
     def __init__(self, order: int, n_init: int, n_inst: int, steps, mode: str = "fp64r",
                  refine_steps: int = -1, chunk: int = 0, block: int = 0, max_blocks: int = 0,
-                 chunk_upper: int = 0):
+                 chunk_upper: int = 0, init_points: int = 1):
         L = _lib.lib()
         if mode not in _lib.MODES:
             raise ValueError("mode must be one of %s" % sorted(_lib.MODES))
@@ -48,12 +50,14 @@ class Plan:
         d.mode, d.refine_steps, d.chunk = _lib.MODES[mode], int(refine_steps), int(chunk)
         d.chunk_upper = int(chunk_upper)
         d.block, d.max_blocks = int(block), int(max_blocks)
+        d.init_points = int(init_points)
         h = ctypes.c_void_p()
         _lib.check(L.smnn_plan_create(ctypes.byref(d), ctypes.byref(h)), "smnn_plan_create")
         self._h = h
         self._L = L
         self.order, self.n_init, self.n_inst, self.mode = int(order), int(n_init), int(n_inst), mode
         self.k = self.order + 1
+        self.init_points = self.query(_lib.Q_INIT_POINTS)
         fb, wb, S = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int64()
         _lib.check(L.smnn_plan_sizes(h, ctypes.byref(fb), ctypes.byref(wb), ctypes.byref(S)), "smnn_plan_sizes")
         self.factor_bytes, self.workspace_bytes, self.total_steps = fb.value, wb.value, S.value
@@ -126,7 +130,7 @@ class Plan:
         self._check("b", b, (S,))
         self._check("h", h, (S,))
         if self.n_init:
-            self._check("u0", u0, (N, self.n_init))
+            self._check("u0", u0, (N, self.init_points, self.n_init))
         self._check("w", w, (N, 3))
 
     def forward(self, c, b, h, u0, w, y, factor, workspace, info=None, stream=None):
@@ -146,7 +150,7 @@ class Plan:
                                ("dh", dh, (S,)), ("dw", dw, (N, 3))):
             self._check(name, t, shape)
         if self.n_init:
-            self._check("du0", du0, (N, self.n_init))
+            self._check("du0", du0, (N, self.init_points, self.n_init))
         st = torch.cuda.current_stream(c.device).cuda_stream if stream is None else stream
         _lib.check(self._L.smnn_backward(self._h, _ptr(c), _ptr(b), _ptr(h), _ptr(u0), _ptr(w), _ptr(y),
                                          _ptr(factor), factor.numel(), _ptr(gy), _ptr(dc), _ptr(db), _ptr(dh),
@@ -157,13 +161,14 @@ class Plan:
 _PLANS: "OrderedDict[tuple, Plan]" = OrderedDict()
 
 
-def get_plan(order, n_init, n_inst, steps, mode="fp64r", refine_steps=-1, chunk=0):
+def get_plan(order, n_init, n_inst, steps, mode="fp64r", refine_steps=-1, chunk=0, init_points=1):
     """Plans are cached per (device, sizes, mode); creating one uploads metadata."""
     key_steps = int(steps) if np.isscalar(steps) else tuple(int(t) for t in steps)
-    key = (torch.cuda.current_device(), order, n_init, n_inst, key_steps, mode, refine_steps, chunk)
+    key = (torch.cuda.current_device(), order, n_init, n_inst, key_steps, mode, refine_steps, chunk, init_points)
     p = _PLANS.get(key)
     if p is None:
-        p = Plan(order, n_init, n_inst, steps, mode=mode, refine_steps=refine_steps, chunk=chunk)
+        p = Plan(order, n_init, n_inst, steps, mode=mode, refine_steps=refine_steps, chunk=chunk,
+                 init_points=init_points)
         _PLANS[key] = p
         while len(_PLANS) > 16:
             _PLANS.popitem(last=False)
@@ -206,8 +211,9 @@ def solve(c, b, h, u0, w, order=None, n_init=None, steps=None, mode="fp64r", ref
     """Differentiable batched solve.
 
     Uniform batches may pass c as (N, T, R+1), b and h as (N, T); otherwise c is
-    (S, R+1), b and h are (S,) and `steps` lists T_i.  u0 is (N, n_init), w is
-    (N, 3).  Returns y with the shape of c.
+    (S, R+1), b and h are (S,) and `steps` lists T_i.  u0 is (N, n_init)
+    (initial values at the first point) or (N, T_init, n_init) (at each of the
+    first T_init points); w is (N, 3).  Returns y with the shape of c.
     """
     shape = c.shape
     if c.dim() == 3:
@@ -221,7 +227,10 @@ def solve(c, b, h, u0, w, order=None, n_init=None, steps=None, mode="fp64r", ref
             raise ValueError("steps is required for the flattened layout")
         c2, b2, h2 = c, b, h
     order = k - 1 if order is None else order
-    n_init = (u0.shape[1] if u0 is not None else 0) if n_init is None else n_init
-    plan = get_plan(order, n_init, N, steps, mode=mode, refine_steps=refine_steps, chunk=chunk)
+    init_points = u0.shape[1] if u0 is not None and u0.dim() == 3 else 1
+    if n_init is None:
+        n_init = u0.shape[-1] if u0 is not None else 0
+    plan = get_plan(order, n_init, N, steps, mode=mode, refine_steps=refine_steps, chunk=chunk,
+                    init_points=init_points)
     y = SmnnSolve.apply(c2, b2, h2, u0, w, plan)
     return y.reshape(shape)

@@ -52,7 +52,7 @@ def _store(cache):
         pass
 
 
-def autotune(order, n_init, n_inst, steps, mode, c, b, h, u0, w, gy, iters=3, use_cache=True):
+def autotune(order, n_init, n_inst, steps, mode, c, b, h, u0, w, gy, iters=3, use_cache=True, init_points=1):
     """Best {chunk, chunk_upper, block, max_blocks, ms} for this problem; the
     candidates timed are returned under 'candidates' when a search ran."""
     key = _key(order, mode, n_inst, steps, c.device)
@@ -70,6 +70,7 @@ def autotune(order, n_init, n_inst, steps, mode, c, b, h, u0, w, gy, iters=3, us
         steps_arr = np.ascontiguousarray(steps, dtype=np.int64)
         d.steps = steps_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     d.mode, d.refine_steps = _lib.MODES[mode], -1
+    d.init_points = int(init_points)
     best = _lib.TuneResult()
     cap = 64
     all_ = (_lib.TuneResult * cap)()

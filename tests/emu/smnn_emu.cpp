@@ -16,10 +16,13 @@ using namespace smnn;
 
 namespace {
 
+int g_init_points = 1;   // T_init of the next calls (emu_set_init_points)
+
 template <int K, int L0, int L1, class TIO>
 struct Emu {
   static constexpr int Q = Dim<K>::Q, KK = Dim<K>::KK, REC = Q + KK;
   int n_init;
+  int t_init = 1;
   std::vector<Level> lv;
   std::vector<std::vector<double>> rec, rhs, x;   // per level >= 1
   const TIO *c, *d, *s, *u0, *w;
@@ -28,7 +31,7 @@ struct Emu {
     Inst<K> p{};
     p.wg = (double)w[3 * i]; p.wi = (double)w[3 * i + 1]; p.ws = (double)w[3 * i + 2];
     p.n_init = n_init;
-    for (int r = 0; r < K; ++r) p.u0[r] = r < n_init ? (double)u0[i * n_init + r] : 0.0;
+    p.t_init = t_init;
     return p;
   }
 
@@ -39,6 +42,8 @@ struct Emu {
     S.c = c + o * K; S.d = d + o; S.s = s + o;
     S.g = g ? g + o * K : nullptr; S.v = v ? v + o * K : nullptr;
     S.n = lv[0].n[i]; S.p = inst(i);
+    S.u = u0;
+    S.uo = static_cast<int>(i * t_init * n_init);
     return S;
   }
 
@@ -145,12 +150,17 @@ struct Emu {
       sink.c = S.c; sink.d = S.d; sink.s = S.s;
       sink.y = y + o * K;
       sink.v = v ? v + o * K : nullptr;
-      sink.dc = dc + o * K; sink.dd = dd + o; sink.ds = ds + o; sink.du0 = du0 + i * n_init;
+      sink.dc = dc + o * K; sink.dd = dd + o; sink.ds = ds + o; sink.du0 = du0 + i * t_init * n_init;
+      sink.u = S.u;
+      sink.uo = S.uo;
       sink.p = S.p;
       if (G.has_right) sink.start(G.b + 1, xr);
       backsub_chunk<K, L0>(S, G.a, G.b, G.has_left, G.has_right, xl, xr, xs, sink);
       if (G.has_left) sink.left(G.a - 1, xl);
-      if (!G.has_right) sink.ds[lvl.n[i] - 1] = (TIO)0;
+      if (!G.has_right) {
+        sink.ds[lvl.n[i] - 1] = (TIO)0;
+        sink.zero_past_end(lvl.n[i]);
+      }
       for (int e = 0; e < 3; ++e) dw_part[ch * 3 + e] = sink.dw[e];
     }
   }
@@ -183,6 +193,7 @@ struct Runner {
                      const TIO* u0, const TIO* w, TIO* y, int refine) {
     Emu<K, L0, L1, TIO> E;
     E.n_init = n_init;
+    E.t_init = g_init_points;
     E.lv = build_levels(std::vector<int64_t>(T, T + N), L0, L1);
     E.c = c; E.d = d; E.s = s; E.u0 = u0; E.w = w;
     E.alloc();
@@ -204,6 +215,7 @@ struct Runner {
                          const TIO* u0, const TIO* w, const TIO* v, TIO* out) {
     Emu<K, L0, L1, TIO> E;
     E.n_init = n_init;
+    E.t_init = g_init_points;
     E.lv = build_levels(std::vector<int64_t>(T, T + N), L0, L1);
     E.c = c; E.d = d; E.s = s; E.u0 = u0; E.w = w;
     E.alloc();
@@ -218,6 +230,7 @@ struct Runner {
                       TIO* du0, TIO* dw, int refine) {
     Emu<K, L0, L1, TIO> E;
     E.n_init = n_init;
+    E.t_init = g_init_points;
     E.lv = build_levels(std::vector<int64_t>(T, T + N), L0, L1);
     E.c = c; E.d = d; E.s = s; E.u0 = u0; E.w = w;
     E.alloc();
@@ -270,6 +283,8 @@ struct Runner {
   if (K == KV && Lc == LV && Lu == 8 && LV != 8) return Runner<KV, LV, 8, TYPE>::FN(__VA_ARGS__);
 
 extern "C" {
+
+void emu_set_init_points(int t) { g_init_points = t > 0 ? t : 1; }
 #define TYPE double
 int emu_forward_f64(int K, int Lc, int Lu, int n_init, int64_t N, const int64_t* T, const double* c, const double* d,
                     const double* s, const double* u0, const double* w, double* y, int refine) {

@@ -41,9 +41,9 @@ def run(bt, mode, gy=None, chunk=0, block=0, max_blocks=0, refine_steps=-1, devi
     dt = dtype_for(mode)
     steps = int(bt.T[0]) if np.all(bt.T == bt.T[0]) else bt.T
     p = Plan(bt.R, bt.n_init, bt.n_inst, steps, mode=mode, chunk=chunk, block=block, max_blocks=max_blocks,
-             refine_steps=refine_steps, chunk_upper=chunk_upper)
+             refine_steps=refine_steps, chunk_upper=chunk_upper, init_points=bt.t_init)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
-    c, b, h, u0, w = t(bt.c), t(bt.b), t(bt.h), t(bt.u0.reshape(bt.n_inst, bt.n_init)), t(bt.w)
+    c, b, h, u0, w = t(bt.c), t(bt.b), t(bt.h), t(bt.u0.reshape(bt.n_inst, bt.t_init * bt.n_init)), t(bt.w)
     y = torch.empty((p.total_steps, p.k), dtype=dt, device=dev)
     fac, ws = p.new_factor(dev), p.new_workspace(dev)
     inf = torch.full((bt.n_inst,), -7, dtype=torch.int32, device=dev) if info else None

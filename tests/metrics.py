@@ -39,11 +39,14 @@ def grad_scales(c, d, s, u0, w, y, lam):
     Fm = (ac * al).sum(1)                      # |f| bound
     sc = wg * wg * (E[:, None] * al + Fm[:, None] * ay)
     sd = wg * wg * Fm
-    n_init = len(u0)
-    su = wi * wi * al[0, :n_init]
+    U = np.abs(np.asarray(u0, dtype=np.float64))
+    U = U.reshape(1, -1) if U.ndim <= 1 else U        # [T_init, n_init]
+    te, n_init = min(U.shape[0], T), U.shape[1]
+    su = np.zeros(U.shape)
+    su[:te] = wi * wi * al[:te, :n_init]
     sw = np.zeros(3)
     sw[0] = 2 * wg * float((E * Fm).sum())
-    sw[1] = 2 * wi * float(((ay[0, :n_init] + np.abs(u0)) * al[0, :n_init]).sum())
+    sw[1] = 2 * wi * float(((ay[:te, :n_init] + U[:te]) * al[:te, :n_init]).sum())
     ss = np.zeros(T)
     if T > 1:
         st = np.abs(np.asarray(s, dtype=np.float64)[:T - 1])
@@ -66,7 +69,7 @@ def grad_scales(c, d, s, u0, w, y, lam):
                 ss[:-1] += ws * ws * (dl * rho + mu * dy)
                 acc_w += rho * mu
         sw[2] = 2 * ws * float(acc_w.sum())
-    return {"dc": sc, "dd": sd, "ds": ss, "du0": su, "dw": sw}
+    return {"dc": sc, "dd": sd, "ds": ss, "du0": su.reshape(np.shape(u0)), "dw": sw}
 
 
 def grad_error(got, ref, scale):

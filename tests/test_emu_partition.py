@@ -100,3 +100,33 @@ def test_partition_schedule_under_address_sanitizer():
     env = dict(os.environ, LD_PRELOAD=asan, ASAN_OPTIONS="detect_leaks=0")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0 and "asan-clean" in r.stdout, r.stderr[-3000:]
+
+
+@pytest.mark.parametrize("t_init,n_init", [(3, 2), (9, 3), (40, 1)])
+def test_partition_schedule_with_several_initial_points(t_init, n_init):
+    # T_init spanning several level-0 chunks, and instances shorter than T_init
+    lib = ctypes.CDLL(_build())
+    T = [3, 4, 5, 9, 16, 17, 33, 100]
+    bt = gaussian_batch(len(T), T, R=2, seed=t_init, n_init=n_init, weights=(1.2, 0.9, 1.3), t_init=t_init)
+    gy = np.random.default_rng(t_init).standard_normal(bt.c.shape)
+    ref = banded.grad(bt, gy)
+    kappa = banded.cond(bt)
+    o = bt.offsets
+    lib.emu_set_init_points(t_init)
+    try:
+        for L, Lu in ((4, 4), (4, 8)):
+            out = emu_run(lib, bt, L, 1, gy, Lu)
+            for i in range(bt.n_inst):
+                sl = slice(o[i], o[i + 1])
+                assert max(metrics.rel_by_order(out["y"][sl], ref["y"][sl], bt.k)) <= 1e-10, (L, i)
+                c, d, s, u0, w = bt.instance(i)
+                sc = metrics.grad_scales(c, d, s, u0, w, ref["y"][sl], ref["lam"][sl])
+                gt = max(1e-10, 10 * kappa[i] * 2.2e-16)
+                for key in ("dc", "dd", "ds"):
+                    assert metrics.grad_error(out[key][sl], ref[key][sl], sc[key]) <= gt, (L, i, key)
+                for key in ("du0", "dw"):
+                    assert metrics.grad_error(out[key][i], ref[key][i], sc[key]) <= gt, (L, i, key)
+                past = out["du0"][i].reshape(t_init, n_init)[bt.T[i]:]
+                assert np.all(past == 0.0)
+    finally:
+        lib.emu_set_init_points(1)

@@ -196,6 +196,34 @@ def test_initial_row_counts(n_init):
         assert worst["du0"] <= max(H.g_tolerance("fp64r", kappa), resolve)
 
 
+@pytest.mark.parametrize("mode", ["fp64", "fp64r", "fp32r"])
+@pytest.mark.parametrize("t_init,n_init", [(2, 2), (9, 3), (40, 1)])
+def test_several_initial_points(mode, t_init, n_init):
+    # Eq. 5 at the first T_init points: T_init inside the first level-0 chunk,
+    # spanning several chunks, and longer than the shortest instances (whose
+    # points past the end carry no row and get du0 = 0)
+    T = [3, 5, 8, 9, 17, 64, 333, 1000]
+    bt = H.io_batch(gaussian_batch(len(T), T, R=2, seed=50 + t_init, n_init=n_init, weights=(1.2, 0.9, 1.3),
+                                   t_init=t_init), mode)
+    gy = np.random.default_rng(t_init).standard_normal(bt.c.shape)
+    if mode == "fp32r":
+        gy = gy.astype(np.float32).astype(np.float64)
+    ref = banded.grad(bt, gy)
+    kappa = banded.cond(bt).max()
+    out = H.run(bt, mode, gy)
+    assert out["plan"].init_points == t_init
+    worst = H.compare(bt, out, ref, range(bt.n_inst))
+    _print("init points %d x %d %s" % (t_init, n_init, mode), " ".join("%s=%.1e" % kv for kv in worst.items()),
+           "kappa<=%.1e" % kappa)
+    assert (out["info"] == 0).all()
+    assert worst["y"] <= H.y_tolerance(mode, kappa)
+    for key in ("dc", "dd", "ds", "du0", "dw"):
+        assert worst[key] <= H.g_tolerance(mode, kappa), key
+    du0 = out["du0"].reshape(bt.n_inst, t_init, n_init)
+    for i, Ti in enumerate(T):
+        assert np.all(du0[i, Ti:] == 0.0)
+
+
 def test_failure_reported_per_instance_and_isolated():
     bt = gaussian_batch(4, [50, 300, 1000, 90], R=2, seed=3)
     clean = H.run(bt, "fp64r")
