@@ -4,13 +4,13 @@
 // device code (the kernels in smnn_kernels.hip) and from host code (the
 // indexing checker in tests/emu).  Notation follows the paper
 // (Scalable Mechanistic Neural Networks):
-//   * one instance = one (batch, variable) pair: V = Q = 1, T_init = 1,
-//     block size K = R + 1;
+//   * one instance = one (batch, variable) pair: V = Q = 1, block size
+//     K = R + 1; initial rows (Eq. 5) at the first T_init nodes;
 //   * node t carries the unknowns y_t (K values);
 //   * M is block tridiagonal (Eq. 10): diagonal blocks A_t ("M_t"),
 //     block (t+1, t) = B_t ("N_t"), right-hand side f_t ("beta_t");
 //   * the blocks come from App. A.2: governing term w_g^2 c_t c_t^T, initial
-//     term w_i^2 U, and the smoothness terms of the rows of Eqs. 6-7
+//     term w_i^2 U_t, and the smoothness terms of the rows of Eqs. 6-7
 //     weighted by w_s s_t^r (the weighting before Eq. 9).
 //
 // Elimination follows the block Cholesky recurrence of Alg. 3 and the
