@@ -109,7 +109,8 @@ typedef struct {
   int32_t block;          /* threads per workgroup (64..256, multiple of 64); 0: 64 */
   int32_t max_blocks;     /* >0: persistent grid-stride launch with at most this many
                              workgroups per kernel; 0: one wavefront per tile */
-  int32_t init_points;    /* T_init: leading time points with initial values (Eq. 5); 0: 1 */
+  int32_t init_points;    /* T_init: leading time points with initial values (Eq. 5); 0: 1.
+                             N * T_init * n_init must not exceed INT32_MAX */
 } smnn_plan_desc;
 
 /* Create a plan on the current HIP device: validates the description,

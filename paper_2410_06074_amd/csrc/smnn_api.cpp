@@ -172,6 +172,8 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   if (d->n_init < 0 || d->n_init > d->order + 1) return SMNN_ERR_INVALID_ARG;
   if (d->init_points < 0 || d->init_points > (1 << 30)) return SMNN_ERR_INVALID_ARG;
   if (d->n_inst < 1 || d->n_inst > INT32_MAX) return SMNN_ERR_INVALID_ARG;
+  // the kernels index the initial values with 32-bit offsets
+  if (d->n_inst * d->n_init > INT32_MAX / std::max(1, d->init_points)) return SMNN_ERR_INVALID_ARG;
   if (d->mode < SMNN_MODE_FP64 || d->mode > SMNN_MODE_FP32_REFINED) return SMNN_ERR_INVALID_ARG;
   if (d->refine_steps < -1 || d->refine_steps > 2) return SMNN_ERR_INVALID_ARG;
   if (d->block < 0 || d->block > 256 || d->block % 64 != 0) return SMNN_ERR_INVALID_ARG;
