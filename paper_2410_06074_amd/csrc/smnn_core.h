@@ -489,6 +489,73 @@ SMNN_HD void reduce_chunk(const Src& src, int64_t a, int64_t b, bool has_left, b
   }
 }
 
+// The right-hand-side half of reduce_chunk for a chunk whose factor is
+// already known (Ls[u] = Cholesky factor of node a+u's reduced diagonal
+// block, as backsub_forward leaves it for the same nodes and matrix): the
+// forward substitution of Alg. 4 over the interior and the separators'
+// right-hand-side pieces rf and lf.  The matrix pieces rA, lA, lB and the
+// pivots are not formed (a right-hand-side-only solve reuses the separator
+// records of the first one).  Bitwise equal to reduce_chunk's rf, lf.
+template <int K, int L, class Src>
+SMNN_HD void reduce_chunk_rhs(const Src& src, int64_t a, int64_t b, bool has_left, bool has_right,
+                              const double (&Ls)[L][Dim<K>::Q], Reduced<K>& out) {
+  constexpr int Q = Dim<K>::Q, KK = Dim<K>::KK;
+  double gh[K], Xh[KK], Lb[Q];
+#pragma unroll
+  for (int e = 0; e < K; ++e) out.lf[e] = 0.0;
+#pragma unroll
+  for (int e = 0; e < KK; ++e) Xh[e] = 0.0;
+  out.fail = 0;
+#pragma unroll
+  for (int u = 0; u < L; ++u) {
+    const int64_t i = a + u;
+    if (i > b) break;
+#pragma unroll
+    for (int e = 0; e < Q; ++e) Lb[e] = Ls[u][e];   // the last node's factor after the loop
+    double A[Q], f[K], Bp[KK];
+    src.load(i, A, f, Bp);                     // A unused
+    double X[KK];
+    if (u == 0) {
+      if (has_left) {
+#pragma unroll
+        for (int e = 0; e < KK; ++e) X[e] = Bp[e];
+      }
+    } else {
+      double (&W)[KK] = Bp;
+      rsolve_t<K>(Ls[u > 0 ? u - 1 : 0], W);   // W = B_{i-1} L_{i-1}^{-T}
+      sub_matvec<K>(W, gh, f);
+      if (has_left) neg_matmul<K>(W, Xh, X);
+    }
+#pragma unroll
+    for (int e = 0; e < K; ++e) gh[e] = f[e];
+    lsolve<K>(Ls[u], gh);
+    if (has_left) {
+#pragma unroll
+      for (int e = 0; e < KK; ++e) Xh[e] = X[e];
+      lsolve_cols<K>(Ls[u], Xh);
+#pragma unroll
+      for (int r = 0; r < K; ++r) {
+        double t = out.lf[r];
+#pragma unroll
+        for (int m = 0; m < K; ++m) t += Xh[m * K + r] * gh[m];
+        out.lf[r] = t;
+      }
+    }
+  }
+  if (has_left) {
+#pragma unroll
+    for (int e = 0; e < K; ++e) out.lf[e] = -out.lf[e];
+  }
+  if (has_right) {
+    double V[KK], A[Q], f[K];
+    src.load(b + 1, A, f, V);                  // V = B_b; A unused
+    rsolve_t<K>(Lb, V);                        // V = B_b L_b^{-T}
+    sub_matvec<K>(V, gh, f);
+#pragma unroll
+    for (int e = 0; e < K; ++e) out.rf[e] = f[e];
+  }
+}
+
 // Receives nothing: the caller reads x afterwards.
 struct NoSink {
   template <int K>

@@ -486,12 +486,22 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDe
     __builtin_amdgcn_s_waitcnt(0);
     // 1. back-substitution: the iterate of every tile chunk into the slice
     //    (lane 0 also stores its left separator's value, the step before the
-    //    tile, which its residual reads)
+    //    tile, which its residual reads).  Where registers allow (KEEP), the
+    //    chunk's factor Ls is kept for the reduce below, which eliminates the
+    //    same nodes of the same matrix; otherwise the reduce refactors.
+    constexpr bool KEEP = K <= 3 && K * L <= 16;   // still 2 waves per SIMD
+    double Ls[KEEP ? L : 1][Dim<K>::Q];
     if (valid) {
       StoreSink<TIO, false> sink{it, nullptr, src.o, src.o};
       if (geo.has_right) sink.template node<K>(geo.b + 1, xr);
       if (lane == 0 && geo.has_left) sink.template node<K>(geo.a - 1, xl);
-      const int fail = backsub_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
+      int fail;
+      if constexpr (KEEP) {
+        fail = backsub_forward<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, Ls, xs);
+        backsub_backward<K, L>(src, geo.a, geo.b, Ls, xs, sink);
+      } else {
+        fail = backsub_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
+      }
       if (fail) report_fail(a, inst, 0, geo.a + fail - 1);
     }
     __builtin_amdgcn_s_waitcnt(0);
@@ -509,8 +519,12 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDe
     for (int e = 0; e < Dim<K>::KK; ++e) red.lB[e] = 0.0;
     red.fail = 0;
     if (valid && g < t1 && (geo.has_left || geo.has_right)) {
-      reduce_chunk<K, L>(rs, geo.a, geo.b, geo.has_left, geo.has_right, red);
-      if (red.fail) report_fail(a, inst, 0, geo.a + red.fail - 1);
+      if constexpr (KEEP) {
+        reduce_chunk_rhs<K, L>(rs, geo.a, geo.b, geo.has_left, geo.has_right, Ls, red);   // pivots reported above
+      } else {
+        reduce_chunk<K, L>(rs, geo.a, geo.b, geo.has_left, geo.has_right, red);
+        if (red.fail) report_fail(a, inst, 0, geo.a + red.fail - 1);
+      }
     }
     exchange_and_write<K>(red, owned && geo.has_left, l1, c1, j - 1, a.L1, false);
     // 3. the owned chunks' iterate out to HBM in whole rows

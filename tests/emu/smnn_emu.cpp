@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <cstring>
 #include <vector>
 
 #include "../../paper_2410_06074_amd/csrc/smnn_core.h"
@@ -210,6 +211,37 @@ struct Runner {
     return 0;
   }
 
+  // Level-0 chunks: the right-hand-side pieces (rf, lf) of reduce_chunk and of
+  // reduce_chunk_rhs given the factor backsub_forward leaves, for the residual
+  // of iterate v.  Returns the number of chunks where they differ in any bit.
+  static int check_reduce_rhs(int n_init, int64_t N, const int64_t* T, const TIO* c, const TIO* d,
+                              const TIO* s, const TIO* u0, const TIO* w, const TIO* v) {
+    Emu<K, L0, L1, TIO> E;
+    E.n_init = n_init;
+    E.t_init = g_init_points;
+    E.lv = build_levels(std::vector<int64_t>(T, T + N), L0, L1);
+    E.c = c; E.d = d; E.s = s; E.u0 = u0; E.w = w;
+    const Level& lvl = E.lv[0];
+    int bad = 0;
+    for (int64_t ch = 0; ch < lvl.chunks; ++ch) {
+      const int64_t i = lvl.chunk_inst[ch];
+      const ChunkGeom G = chunk_geom(ch - lvl.chunk_off[i], lvl.n[i], L0);
+      if (!G.has_left && !G.has_right) continue;
+      double xl[K] = {}, xr[K] = {}, xs[L0][K], Ls[L0][Dim<K>::Q];
+      const auto S0 = E.template src0<RHS_RESID>(i, nullptr, v);
+      backsub_forward<K, L0>(S0, G.a, G.b, G.has_left, G.has_right, xl, xr, Ls, xs);
+      Reduced<K> r1{}, r2{};
+      const auto S1 = E.template src0<RHS_RESID>(i, nullptr, v);
+      reduce_chunk<K, L0>(S1, G.a, G.b, G.has_left, G.has_right, r1);
+      const auto S2 = E.template src0<RHS_RESID>(i, nullptr, v);
+      reduce_chunk_rhs<K, L0>(S2, G.a, G.b, G.has_left, G.has_right, Ls, r2);
+      if ((G.has_right && std::memcmp(r1.rf, r2.rf, sizeof(r1.rf)) != 0) ||
+          (G.has_left && std::memcmp(r1.lf, r2.lf, sizeof(r1.lf)) != 0))
+        ++bad;
+    }
+    return bad;
+  }
+
   // one refinement pass from a given iterate v: out = v + M^{-1} A^T W (b - A v)
   static int refine_from(int n_init, int64_t N, const int64_t* T, const TIO* c, const TIO* d, const TIO* s,
                          const TIO* u0, const TIO* w, const TIO* v, TIO* out) {
@@ -285,7 +317,18 @@ struct Runner {
 extern "C" {
 
 void emu_set_init_points(int t) { g_init_points = t > 0 ? t : 1; }
+
 #define TYPE double
+
+int emu_check_reduce_rhs_f64(int K, int Lc, int Lu, int n_init, int64_t N, const int64_t* T, const double* c,
+                             const double* d, const double* s, const double* u0, const double* w, const double* v) {
+  DISPATCH(2, 4, check_reduce_rhs, n_init, N, T, c, d, s, u0, w, v)
+  DISPATCH(2, 8, check_reduce_rhs, n_init, N, T, c, d, s, u0, w, v)
+  DISPATCH(3, 4, check_reduce_rhs, n_init, N, T, c, d, s, u0, w, v)
+  DISPATCH(3, 8, check_reduce_rhs, n_init, N, T, c, d, s, u0, w, v)
+  return -1;
+}
+
 int emu_forward_f64(int K, int Lc, int Lu, int n_init, int64_t N, const int64_t* T, const double* c, const double* d,
                     const double* s, const double* u0, const double* w, double* y, int refine) {
   DISPATCH(2, 4, forward, n_init, N, T, c, d, s, u0, w, y, refine)

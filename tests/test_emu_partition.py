@@ -130,3 +130,18 @@ def test_partition_schedule_with_several_initial_points(t_init, n_init):
                 assert np.all(past == 0.0)
     finally:
         lib.emu_set_init_points(1)
+
+
+@pytest.mark.parametrize("R,L", [(2, 4), (1, 8), (2, 8)])
+def test_reduce_with_known_factor_matches_full_reduce(R, L):
+    # the fused back-substitution + reduce kernel reuses the chunk factor of
+    # its back-substitution: its separator right-hand sides must equal those
+    # of the full reduce bit for bit
+    lib = ctypes.CDLL(_build())
+    bt = gaussian_batch(len(EDGE_T), EDGE_T, R=R, seed=90 + L, weights=(1.2, 0.7, 1.4))
+    v = np.random.default_rng(L).standard_normal(bt.c.shape)
+    T = np.ascontiguousarray(bt.T, dtype=np.int64)
+    u0 = np.ascontiguousarray(bt.u0)
+    bad = lib.emu_check_reduce_rhs_f64(bt.k, L, L, bt.n_init, ctypes.c_int64(bt.n_inst), T.ctypes.data_as(_IP),
+                                       _p(bt.c), _p(bt.b), _p(bt.h), _p(u0), _p(bt.w), _p(v))
+    assert bad == 0
