@@ -75,6 +75,8 @@ def kernel_bytes(rec, plan, io):
     if kind == "backsub_reduce0":          # rhs = the solve's form (beta or dl/dy)
         el = K + 1 + (1 if rhs == RHS_BETA else 0) + (K if rhs == RHS_G else 0)
         return S * el * io + per_inst + n(1) * K * 8 + K * S * io + n(1) * K * 8
+    if kind == "top":                      # levels >= level: its records and rhs in, its x out
+        return n(level) * (REC + K) * 8 + n(level) * K * 8
     if kind == "dw_reduce":
         return G0 * 3 * 8 + N * 3 * io
     return 0

@@ -127,14 +127,15 @@ smnn_status smnn_plan_sizes(const smnn_plan* plan, size_t* factor_bytes, size_t*
                             int64_t* total_steps);
 
 /* Introspection: SMNN_Q_LEVELS, SMNN_Q_CHUNK, SMNN_Q_CHUNK_UPPER, SMNN_Q_NODES(l),
- * SMNN_Q_CHUNKS(l), SMNN_Q_REFINE, SMNN_Q_MODE, SMNN_Q_INIT_POINTS.  Returns -1 for an
- * unknown key. */
+ * SMNN_Q_CHUNKS(l), SMNN_Q_REFINE, SMNN_Q_MODE, SMNN_Q_INIT_POINTS, SMNN_Q_TOP_LEVEL.
+ * Returns -1 for an unknown key. */
 #define SMNN_Q_LEVELS 1
 #define SMNN_Q_CHUNK 2
 #define SMNN_Q_REFINE 3
 #define SMNN_Q_MODE 4
 #define SMNN_Q_CHUNK_UPPER 5
 #define SMNN_Q_INIT_POINTS 6
+#define SMNN_Q_TOP_LEVEL 7    /* first level solved by the one-wave-per-instance launch (0: none) */
 #define SMNN_Q_NODES(l) (1000 + (l))
 #define SMNN_Q_CHUNKS(l) (2000 + (l))
 int64_t smnn_plan_query(const smnn_plan* plan, int32_t key);
@@ -179,6 +180,7 @@ typedef struct {
 #define SMNN_K_DW 5
 #define SMNN_K_INFO 6
 #define SMNN_K_BACKSUB_REDUCE0 7   /* level-0 back-substitution fused with the next solve's level-0 reduce */
+#define SMNN_K_TOP 8               /* every separator level from `level` up, one wave per instance */
 smnn_status smnn_trace_enable(smnn_plan* plan, int32_t capacity);
 int32_t smnn_trace_read(smnn_plan* plan, smnn_trace_record* out, int32_t cap);
 

@@ -13,7 +13,7 @@ MODES = {"fp64": 0, "fp64r": 1, "fp32r": 2}
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported order or chunk length",
           3: "workspace or factor too small", 4: "HIP runtime error", 5: "wrong current device"}
 
-Q_LEVELS, Q_CHUNK, Q_REFINE, Q_MODE, Q_CHUNK_UPPER, Q_INIT_POINTS = 1, 2, 3, 4, 5, 6
+Q_LEVELS, Q_CHUNK, Q_REFINE, Q_MODE, Q_CHUNK_UPPER, Q_INIT_POINTS, Q_TOP_LEVEL = 1, 2, 3, 4, 5, 6, 7
 
 
 class SmnnError(RuntimeError):
@@ -28,7 +28,7 @@ class TraceRecord(ctypes.Structure):
 
 
 KERNEL_NAMES = {1: "reduce0", 2: "reduceN", 3: "backsubN", 4: "backsub0", 5: "dw_reduce", 6: "info",
-                7: "backsub_reduce0"}
+                7: "backsub_reduce0", 8: "top"}
 
 
 class TuneResult(ctypes.Structure):

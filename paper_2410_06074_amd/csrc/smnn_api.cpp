@@ -16,6 +16,7 @@ using namespace smnn;
 struct smnn_plan {
   int R = 0, K = 0, n_init = 0, mode = 0, refine = 0, L0 = 8, L1 = 8;
   int t_init = 1;   // time points carrying initial values
+  int top = 0;      // > 0: levels >= top are solved by one launch per solve (launch_top)
   int64_t N = 0, S = 0;
   int device = 0;
   bool f32 = false;
@@ -109,14 +110,17 @@ struct Tracer {
 smnn_status solve_upper(const smnn_plan* p, const Bound& b, int rhs, bool write_rec, const Level0Args& a,
                         hipStream_t st, bool skip_reduce0 = false) {
   const int nl = static_cast<int>(b.lev.size());
+  const int lt = p->top > 0 ? p->top : nl;   // levels >= lt in one launch
   const Tracer tr{p, st};
   if (nl > 1 && !skip_reduce0)
     SMNN_LAUNCH(tr, SMNN_K_REDUCE0, 0, rhs, 0,
                 launch_reduce0(p->K, p->L0, p->f32, rhs, write_rec, b.lev[0], b.lev[1], a, p->cfg, st));
-  for (int l = 1; l + 1 < nl; ++l)
+  for (int l = 1; l + 1 < nl && l < lt; ++l)
     SMNN_LAUNCH(tr, SMNN_K_REDUCEN, l, rhs, 0,
                 launch_reduceN(p->K, p->L1, write_rec, l, b.lev[l], b.lev[l + 1], a, p->cfg, st));
-  for (int l = nl - 1; l >= 1; --l)
+  if (lt < nl)
+    SMNN_LAUNCH(tr, SMNN_K_TOP, lt, rhs, 0, launch_top(p->K, p->L1, lt, b.lev[lt], a, p->cfg, st));
+  for (int l = (lt < nl ? lt : nl) - 1; l >= 1; --l)
     SMNN_LAUNCH(tr, SMNN_K_BACKSUBN, l, rhs, 0,
                 launch_backsubN(p->K, p->L1, l, b.lev[l], l + 1 < nl ? &b.lev[l + 1] : nullptr, a, p->cfg, st));
   return SMNN_OK;
@@ -225,6 +229,20 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
 
   std::vector<Level> lv = build_levels(T, L0, L1);
   p->S = lv[0].nodes;
+  // The upper levels of a solve are short dependent chains: from the first
+  // level >= 1 at which every instance has at most 64 chunks and the level
+  // holds at most 2^19 nodes, they are solved by one launch per solve (one
+  // wave per instance), when that replaces at least two levels.  Only where
+  // that kernel keeps its state in VGPRs (block size <= 3, K * L1 <= 24):
+  // measured faster on the 1536 x 1,000 and 1536 x 10,000 batches, slower
+  // when it starts at a level of millions of nodes or spills into AGPRs.
+  if (K <= 3 && K * L1 <= 24 && top_lds_bytes(K, L1) <= static_cast<size_t>(lds_max)) {
+    for (size_t l = 1; l + 1 < lv.size() && p->top == 0; ++l) {
+      int64_t gmax = 0;
+      for (int64_t i = 0; i < d->n_inst; ++i) gmax = std::max(gmax, lv[l].chunk_off[i + 1] - lv[l].chunk_off[i]);
+      if (gmax <= 64 && lv[l].nodes <= (int64_t(1) << 19)) p->top = static_cast<int>(l);
+    }
+  }
   const int Q = K * (K + 1) / 2, REC = Q + K * K;
   const size_t io = p->f32 ? sizeof(float) : sizeof(double);
 
@@ -361,6 +379,7 @@ int64_t smnn_plan_query(const smnn_plan* p, int32_t key) {
   if (key == SMNN_Q_REFINE) return p->refine;
   if (key == SMNN_Q_MODE) return p->mode;
   if (key == SMNN_Q_INIT_POINTS) return p->t_init;
+  if (key == SMNN_Q_TOP_LEVEL) return p->top;
   if (key >= 1000 && key < 1000 + static_cast<int32_t>(p->lev.size())) return p->lev[key - 1000].nodes;
   if (key >= 2000 && key < 2000 + static_cast<int32_t>(p->lev.size())) return p->lev[key - 2000].chunks;
   return -1;

@@ -70,6 +70,11 @@ hipError_t launch_backsub0(int K, int L, bool f32, int rhs_mode, int out_mode, c
 // iterate; writes the level-1 right-hand sides only).
 hipError_t launch_backsub_reduce0(int K, int L, bool f32, int rhs_in, const LevelDev& l0, const LevelDev& l1,
                                   const Level0Args& a, const Launch& cfg, hipStream_t st);
+// Levels >= level of a solve in one launch, one wave per instance (every
+// instance must have at most 64 chunks at that level); writes that level's x.
+hipError_t launch_top(int K, int L, int level, const LevelDev& l, const Level0Args& a, const Launch& cfg,
+                      hipStream_t st);
+size_t top_lds_bytes(int K, int L);   // per wave
 hipError_t launch_dw_reduce(bool f32, const LevelDev& l0, const Level0Args& a, hipStream_t st);
 hipError_t launch_info_init(const Level0Args& a, hipStream_t st);
 

@@ -534,6 +534,213 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDe
   }
 }
 
+// ------------------------------------- levels >= lt: one wave per instance
+// Used when every instance has at most 64 chunks at level lt.  A wave takes
+// one instance: each lane reduces one level-lt chunk from HBM, the separator
+// systems of the levels above (at most 63, 15, 3 nodes for L = 4) are kept
+// in LDS in the natural layout and reduced there while they have more than
+// one chunk, lane 0 solves the top one, and the back-substitutions come
+// down to level lt, whose solution goes to HBM.  One launch replaces the
+// reduce and back-substitution launches of levels lt and above; the upper
+// levels' records are rebuilt in LDS by every solve rather than stored.
+template <int L>
+struct TopCaps {   // separator nodes one instance can have at LDS levels 1..3
+  static constexpr int c1 = WAVE - 1;
+  static constexpr int c2 = c1 > L ? (c1 + L - 1) / L - 1 : 0;
+  static constexpr int c3 = c2 > L ? (c2 + L - 1) / L - 1 : 0;
+  static_assert(c3 <= L, "the top is reached within three LDS levels");
+  static constexpr int nodes = c1 + c2 + c3;
+};
+
+template <int K>
+struct TopLevel {
+  double* rec;   // [cap][Q + KK]
+  double* rhs;   // [cap][K]
+  double* x;     // [cap][K]
+};
+
+template <int K, int L>
+__device__ __forceinline__ TopLevel<K> top_level(double* base, int d) {
+  using C = TopCaps<L>;
+  constexpr int REC = Dim<K>::Q + Dim<K>::KK;
+  const int off = d == 1 ? 0 : (d == 2 ? C::c1 : C::c1 + C::c2);
+  const int cap = d == 1 ? C::c1 : (d == 2 ? C::c2 : C::c3);
+  double* p = base + off * (REC + 2 * K);
+  return {p, p + cap * REC, p + cap * (REC + K)};
+}
+
+// Nodes of LDS level d of an instance with G chunks at level lt.
+template <int L>
+__device__ __forceinline__ int64_t top_nodes(int G, int d) {
+  int64_t n = G - 1;
+  for (int k = 1; k < d; ++k) n = (n + L - 1) / L - 1;
+  return n;
+}
+
+// Separator m of the level just reduced = node m of LDS level `to`: lane
+// m + 1 combines the right pieces of lane m with its own left pieces.  All
+// 64 lanes must call this.
+template <int K>
+__device__ __forceinline__ void top_combine(const Reduced<K>& red, bool writer, const TopLevel<K>& to, int m) {
+  constexpr int Q = Dim<K>::Q, KK = Dim<K>::KK;
+  double rA[Q], rf[K];
+#pragma unroll
+  for (int e = 0; e < Q; ++e) rA[e] = __shfl_up(red.rA[e], 1, WAVE);
+#pragma unroll
+  for (int e = 0; e < K; ++e) rf[e] = __shfl_up(red.rf[e], 1, WAVE);
+  if (writer) combine_separator<K>(rA, rf, red, to.rec + m * (Q + KK), to.rhs + m * K, true);
+}
+
+template <int K>
+__device__ __forceinline__ void zero_reduced(Reduced<K>& red) {
+#pragma unroll
+  for (int e = 0; e < Dim<K>::Q; ++e) { red.rA[e] = 0.0; red.lA[e] = 0.0; }
+#pragma unroll
+  for (int e = 0; e < K; ++e) { red.rf[e] = 0.0; red.lf[e] = 0.0; }
+#pragma unroll
+  for (int e = 0; e < Dim<K>::KK; ++e) red.lB[e] = 0.0;
+  red.fail = 0;
+}
+
+template <int K, int L>
+__global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_top(LevelDev lv, Level0Args a, int level) {
+  constexpr int PER = Dim<K>::Q + Dim<K>::KK + 2 * K;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* base = reinterpret_cast<double*>(smem) + (threadIdx.x / WAVE) * (TopCaps<L>::nodes * PER);
+  const int lane = lane_id();
+  for (int64_t inst = wave_id(a); inst < a.N; inst += wave_count(a)) {
+    const int64_t off = lv.node_off[inst];
+    const int64_t n = lv.node_off[inst + 1] - off;
+    const int64_t c0 = lv.chunk_off[inst];
+    const int G = static_cast<int>(lv.chunk_off[inst + 1] - c0);   // <= 64 (checked on the host)
+    if (n == 0) continue;
+    double xl[K], xr[K], xs[L][K];
+    if (G > 1) {
+      // 1. level lt: lane j reduces chunk j; separators into LDS level 1
+      {
+        const ChunkGeom geo = chunk_geom(lane, n, L);
+        Reduced<K> red;
+        zero_reduced<K>(red);
+        if (lane < G) {
+          SrcT<K> S;
+          S.rec = lv.rec;
+          S.rhs = lv.rhs;
+          S.C = c0 + lane;
+          S.a = geo.a;
+          S.L = L;
+          reduce_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, red);
+          if (red.fail) report_fail(a, inst, level, geo.a + red.fail - 1);
+        }
+        top_combine<K>(red, lane > 0 && lane < G, top_level<K, L>(base, 1), lane - 1);
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+      // 2. reduce the LDS levels until one is a single chunk
+      int d = 1;
+      int64_t nl = G - 1;
+      while (nl > L) {
+        const int Gd = static_cast<int>((nl + L - 1) / L);
+        const TopLevel<K> cur = top_level<K, L>(base, d);
+        const ChunkGeom geo = chunk_geom(lane, nl, L);
+        Reduced<K> red;
+        zero_reduced<K>(red);
+        if (lane < Gd) {
+          SrcN<K> S{cur.rec, cur.rhs};
+          reduce_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, red);
+          if (red.fail) report_fail(a, inst, level + d, geo.a + red.fail - 1);
+        }
+        top_combine<K>(red, lane > 0 && lane < Gd, top_level<K, L>(base, d + 1), lane - 1);
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        nl = Gd - 1;
+        ++d;
+      }
+      // 3. the top level: a single chunk, solved by lane 0
+      {
+        const TopLevel<K> top = top_level<K, L>(base, d);
+        if (lane == 0) {
+#pragma unroll
+          for (int e = 0; e < K; ++e) { xl[e] = 0.0; xr[e] = 0.0; }
+          SrcN<K> S{top.rec, top.rhs};
+          const int fail = backsub_chunk<K, L>(S, 0, nl - 1, false, false, xl, xr, xs);
+          if (fail) report_fail(a, inst, level + d, fail - 1);
+#pragma unroll
+          for (int u = 0; u < L; ++u)
+            if (u < nl) {
+#pragma unroll
+              for (int e = 0; e < K; ++e) top.x[u * K + e] = xs[u][e];
+            }
+        }
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+      // 4. back-substitute the LDS levels below the top
+      for (int dd = d - 1; dd >= 1; --dd) {
+        const TopLevel<K> cur = top_level<K, L>(base, dd), up = top_level<K, L>(base, dd + 1);
+        const int64_t nd = top_nodes<L>(G, dd);
+        const int Gd = static_cast<int>((nd + L - 1) / L);
+        if (lane < Gd) {
+          const ChunkGeom geo = chunk_geom(lane, nd, L);
+#pragma unroll
+          for (int e = 0; e < K; ++e) {
+            xl[e] = geo.has_left ? up.x[(lane - 1) * K + e] : 0.0;
+            xr[e] = geo.has_right ? up.x[lane * K + e] : 0.0;
+          }
+          SrcN<K> S{cur.rec, cur.rhs};
+          const int fail = backsub_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs);
+          if (fail) report_fail(a, inst, level + dd, geo.a + fail - 1);
+#pragma unroll
+          for (int u = 0; u < L; ++u) {
+            const int64_t t = geo.a + u;
+            if (t > geo.b) break;
+#pragma unroll
+            for (int e = 0; e < K; ++e) cur.x[t * K + e] = xs[u][e];
+          }
+          if (geo.has_right) {
+#pragma unroll
+            for (int e = 0; e < K; ++e) cur.x[(geo.b + 1) * K + e] = xr[e];
+          }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    // 5. level lt: back-substitute every chunk into HBM
+    if (lane < G) {
+      const ChunkGeom geo = chunk_geom(lane, n, L);
+      const TopLevel<K> up = top_level<K, L>(base, 1);
+#pragma unroll
+      for (int e = 0; e < K; ++e) {
+        xl[e] = geo.has_left ? up.x[(lane - 1) * K + e] : 0.0;
+        xr[e] = geo.has_right ? up.x[lane * K + e] : 0.0;
+      }
+      SrcT<K> S;
+      S.rec = lv.rec;
+      S.rhs = lv.rhs;
+      S.C = c0 + lane;
+      S.a = geo.a;
+      S.L = L;
+      const int fail = backsub_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs);
+      if (fail) report_fail(a, inst, level, geo.a + fail - 1);
+      double* x = lv.x + off * K;
+#pragma unroll
+      for (int u = 0; u < L; ++u) {
+        const int64_t t = geo.a + u;
+        if (t > geo.b) break;
+#pragma unroll
+        for (int e = 0; e < K; ++e) x[t * K + e] = xs[u][e];
+      }
+      if (geo.has_right) {
+#pragma unroll
+        for (int e = 0; e < K; ++e) x[(geo.b + 1) * K + e] = xr[e];
+      }
+    }
+    // the next instance reuses the LDS slice
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 int64_t grid_for(int64_t tiles, const Launch& cfg) {
   const int64_t waves_per_block = cfg.block / WAVE;
   int64_t blocks = (tiles + waves_per_block - 1) / waves_per_block;
@@ -686,6 +893,27 @@ hipError_t backsubN_t(int level, const LevelDev& l, const LevelDev* nx, const Le
   return hipGetLastError();
 }
 
+template <int K, int L>
+size_t top_lds_bytes_t() {
+  return sizeof(double) * TopCaps<L>::nodes * (Dim<K>::Q + Dim<K>::KK + 2 * K);
+}
+
+template <int K, int L>
+hipError_t top_t(int level, const LevelDev& l, const Level0Args& a, const Launch& cfg, hipStream_t st) {
+  const size_t wb = top_lds_bytes_t<K, L>();
+  int wpb = cfg.block / WAVE;
+  while (wpb > 1 && wb * static_cast<size_t>(wpb) > static_cast<size_t>(cfg.lds_max)) --wpb;
+  if (wb > static_cast<size_t>(cfg.lds_max)) return hipErrorInvalidConfiguration;
+  Launch c = cfg;
+  c.block = wpb * WAVE;
+  const dim3 grid(static_cast<unsigned>(grid_for(a.N, c))), block(c.block);   // one wave per instance
+  Level0Args b = a;
+  b.wpb = wpb;
+  b.nwaves = static_cast<int64_t>(grid.x) * wpb;
+  hipLaunchKernelGGL((k_top<K, L>), grid, block, wb * wpb, st, l, b, level);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // (K, L) pairs compiled in: L is the chunk length of every level.
@@ -763,6 +991,23 @@ hipError_t SMNN_KFN(launch_backsubN)(int K, int L, int level, const LevelDev& l,
                            const Level0Args& a, const Launch& cfg, hipStream_t st) {
 #define X(KV, LV) \
   if (K == KV && L == LV) return backsubN_t<KV, LV>(level, l, lnext, a, cfg, st);
+  SMNN_FOR_EACH_KL(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+size_t SMNN_KFN(top_lds_bytes)(int K, int L) {
+#define X(KV, LV) \
+  if (K == KV && L == LV) return top_lds_bytes_t<KV, LV>();
+  SMNN_FOR_EACH_KL(X)
+#undef X
+  return 0;
+}
+
+hipError_t SMNN_KFN(launch_top)(int K, int L, int level, const LevelDev& l, const Level0Args& a, const Launch& cfg,
+                                hipStream_t st) {
+#define X(KV, LV) \
+  if (K == KV && L == LV) return top_t<KV, LV>(level, l, a, cfg, st);
   SMNN_FOR_EACH_KL(X)
 #undef X
   return hipErrorInvalidValue;

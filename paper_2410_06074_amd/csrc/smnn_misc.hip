@@ -80,7 +80,9 @@ hipError_t launch_info_finalize(const Level0Args& a, int32_t* info, hipStream_t 
                                    const Launch&, hipStream_t);                                          \
   size_t level0_lds_bytes_k##KV(int, int, bool, int, int);                                                \
   hipError_t launch_backsub_reduce0_k##KV(int, int, bool, int, const LevelDev&, const LevelDev&,          \
-                                          const Level0Args&, const Launch&, hipStream_t);
+                                          const Level0Args&, const Launch&, hipStream_t);                \
+  size_t top_lds_bytes_k##KV(int, int);                                                                   \
+  hipError_t launch_top_k##KV(int, int, int, const LevelDev&, const Level0Args&, const Launch&, hipStream_t);
 SMNN_DECL(2)
 SMNN_DECL(3)
 SMNN_DECL(4)
@@ -132,6 +134,17 @@ hipError_t launch_reduceN(int K, int L, bool write_rec, int level, const LevelDe
 hipError_t launch_backsubN(int K, int L, int level, const LevelDev& l, const LevelDev* lnext,
                            const Level0Args& a, const Launch& cfg, hipStream_t st) {
   SMNN_SWITCH(launch_backsubN, K, L, level, l, lnext, a, cfg, st)
+  return hipErrorInvalidValue;
+}
+
+size_t top_lds_bytes(int K, int L) {
+  SMNN_SWITCH(top_lds_bytes, K, L)
+  return 0;
+}
+
+hipError_t launch_top(int K, int L, int level, const LevelDev& l, const Level0Args& a, const Launch& cfg,
+                      hipStream_t st) {
+  SMNN_SWITCH(launch_top, K, L, level, l, a, cfg, st)
   return hipErrorInvalidValue;
 }
 

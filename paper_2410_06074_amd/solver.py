@@ -83,6 +83,11 @@ class Plan:
     def refine_steps(self):
         return self.query(_lib.Q_REFINE)
 
+    @property
+    def top_level(self):
+        """First level solved by the one-wave-per-instance launch (0: none)."""
+        return self.query(_lib.Q_TOP_LEVEL)
+
     def trace(self, capacity: int):
         """Record a hipEvent pair around each of the next `capacity` launches."""
         _lib.check(self._L.smnn_trace_enable(self._h, int(capacity)), "smnn_trace_enable")

@@ -224,6 +224,28 @@ def test_several_initial_points(mode, t_init, n_init):
         assert np.all(du0[i, Ti:] == 0.0)
 
 
+@pytest.mark.parametrize("mode", ["fp64r", "fp32r"])
+def test_upper_levels_in_one_launch(mode):
+    # chunks 4 / 4: T = 1028 gives 64 level-1 chunks (the most one wave
+    # takes), so the in-LDS levels hold 63, 15 and 3 nodes; adding T = 1100
+    # (69 chunks) moves the one-wave-per-instance launch up to level 2
+    for T, top in (([5, 17, 65, 257, 1000, 1025, 1028], 1), ([5, 17, 65, 257, 1028, 1100], 2)):
+        bt = H.io_batch(gaussian_batch(len(T), T, R=2, seed=len(T) + top, weights=(1.1, 0.9, 1.2)), mode)
+        gy = np.random.default_rng(top).standard_normal(bt.c.shape)
+        if mode == "fp32r":
+            gy = gy.astype(np.float32).astype(np.float64)
+        ref = banded.grad(bt, gy)
+        kappa = banded.cond(bt).max()
+        out = H.run(bt, mode, gy, chunk=4, chunk_upper=4)
+        assert out["plan"].top_level == top
+        worst = H.compare(bt, out, ref, range(bt.n_inst))
+        _print("upper levels %s top=%d" % (mode, top), " ".join("%s=%.1e" % kv for kv in worst.items()))
+        assert (out["info"] == 0).all()
+        assert worst["y"] <= H.y_tolerance(mode, kappa)
+        for key in ("dc", "dd", "ds", "du0", "dw"):
+            assert worst[key] <= H.g_tolerance(mode, kappa), key
+
+
 def test_failure_reported_per_instance_and_isolated():
     bt = gaussian_batch(4, [50, 300, 1000, 90], R=2, seed=3)
     clean = H.run(bt, "fp64r")
