@@ -337,8 +337,8 @@ def main():
     if args.lorenz:
         return lorenz_step_times()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the solve is per-instance independent and this build has no "
-              "multi-GPU path (see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: instances are solved independently and there is no "
+              "multi-GPU path; run with --gpus 1", file=sys.stderr)
         return 2
     import torch
     if not torch.cuda.is_available():

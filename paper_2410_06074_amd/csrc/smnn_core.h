@@ -2,7 +2,7 @@
 //
 // Everything here is a pure function of register arrays, usable from HIP
 // device code (the kernels in smnn_kernels.hip) and from host code (the
-// indexing checker in tests/emu).  Notation follows the paper
+// CPU emulator in tests/emu).  Notation follows the paper
 // (Scalable Mechanistic Neural Networks):
 //   * one instance = one (batch, variable) pair: V = Q = 1, block size
 //     K = R + 1; initial rows (Eq. 5) at the first T_init nodes;
@@ -888,10 +888,10 @@ struct GradSink {
   }
 };
 
-// Node data of a reduced (separator) level in the natural layout (one record
-// per node, as the host checker in tests/emu keeps them; the kernels use the
-// interleaved layout of SrcT): rec[node] = {A packed (Q), B = block
-// (node+1, node) (K*K)}.
+// Node data of a reduced (separator) level in the natural layout: one
+// record per node, as the CPU emulator in tests/emu and the upper-level
+// kernel's LDS keep them (the other kernels use the interleaved layout of
+// SrcT).  rec[node] = {A packed (Q), B = block (node+1, node) (K*K)}.
 template <int K>
 struct SrcN {
   const double* rec;  // [n][Q + KK] of this instance

@@ -176,7 +176,7 @@ def test_closed_form_gradients_match_autograd(R, T, n_init, weights):
     scale = np.linalg.norm(np.concatenate([ref[k].ravel() for k in ("dc", "dd", "ds", "du0")]))
     for key in ("dc", "dd", "ds", "du0", "dw"):
         err = np.linalg.norm(ours[key] - ref[key])
-        # dw is a sum of many cancelling row terms: judge it against the scale of the others
+        # dw is a sum of many cancelling row terms: measure it against the scale of the others
         denom = np.linalg.norm(ref[key]) if key != "dw" else max(np.linalg.norm(ref[key]), scale)
         assert err <= tol * denom, (key, err / denom, tol)
 
