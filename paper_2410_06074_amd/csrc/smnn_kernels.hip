@@ -330,9 +330,17 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsubN(LevelDev lv, L
 }
 
 // ------------------------------------------------------- level 0 back-subst.
+// Waves per SIMD the compiler must fit the kernel into.  The gradient pass at
+// block size 3 and chunk 8 needs 256 VGPRs plus ~56 AGPRs (one wave per
+// SIMD); held to two waves it spills a little and measured 9 % faster.
+template <int K, int L, int OUT>
+struct Backsub0Waves {
+  static constexpr int value = (K == 3 && L == 8 && OUT == OUT_GRAD) ? 2 : SMNN_MIN_WAVES;
+};
+
 template <int K, int L, class TIO, int RHS, int OUT>
-__global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub0(LevelDev l0, LevelDev l1, bool has_next,
-                                                                  Level0Args a) {
+__global__ void __launch_bounds__(256, (Backsub0Waves<K, L, OUT>::value)) k_backsub0(LevelDev l0, LevelDev l1,
+                                                                                     bool has_next, Level0Args a) {
   constexpr bool ADD = (RHS == RHS_RESID || RHS == RHS_GRESID);
   using ST = Stage<K, L, TIO, RHS, OUT>;
   extern __shared__ __align__(16) unsigned char smem[];
