@@ -56,10 +56,19 @@ constexpr int WAVE = 64;
 
 // Wave index and wave count of the launch (wave-uniform values; the launch
 // shape comes in through the arguments so no dispatch-packet loads precede
-// the first memory requests).
+// the first memory requests).  Workgroups are dispatched round-robin over
+// the 8 XCDs (workgroup b runs on XCD b % 8); the wave index gives each
+// XCD a contiguous range of tiles, so that neighbouring tiles, which share
+// boundary rows and write the two halves of some 64-byte runs, meet in the
+// same L2.  The map is a bijection of [0, nwaves).
+constexpr int XCDS = 8;
 __device__ __forceinline__ int64_t wave_id(const Level0Args& a) {
   const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / WAVE);
-  return static_cast<int64_t>(blockIdx.x) * a.wpb + w;
+  const int64_t nb = a.nwaves / a.wpb;
+  const int64_t b = blockIdx.x;
+  const int64_t q = nb / XCDS, r = nb % XCDS, x = b % XCDS, k = b / XCDS;
+  const int64_t vb = x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+  return vb * a.wpb + w;
 }
 __device__ __forceinline__ int64_t wave_count(const Level0Args& a) { return a.nwaves; }
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
