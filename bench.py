@@ -256,6 +256,27 @@ def copy_calibration():
     return 0
 
 
+def copy_rate(reps=20):
+    """The calibration copy timed with events: the read + write rate that a
+    plain streaming kernel reaches on this GPU."""
+    import torch
+    n = 64 * 1024 * 1024
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    print(json.dumps({"copy_bytes_per_direction": n * 8, "copy_ms": round(ms, 4),
+                      "copy_gbs_read_plus_write": round(2 * n * 8 / (ms * 1e-3) / 1e9, 1)}), flush=True)
+    return 0
+
+
 def roofline(res):
     dom_key, dom = max(res["per_kind"].items(), key=lambda kv: kv[1]["ms"])
     avg_ms = dom["ms"] / dom["n"]
@@ -328,12 +349,16 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: library default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--copy-rate", action="store_true",
+                    help="only time that copy: the read + write rate a plain streaming kernel reaches")
     ap.add_argument("--lorenz", action="store_true",
                     help="only time the Lorenz discovery training step (Alg. 5) on the batch / window grid of "
                          "the paper's Lorenz performance table")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration()
+    if args.copy_rate:
+        return copy_rate()
     if args.lorenz:
         return lorenz_step_times()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
