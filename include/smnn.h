@@ -65,9 +65,9 @@
  * on the host before anything is enqueued.  Numerical breakdown is reported
  * per instance through `info` (optional, device int32 [N]): 0 if every pivot
  * of that instance was > 0, else 1 + the time step (0-based) of a pivot that
- * was not (the smallest such step among those met); that instance's outputs
- * are then NaN or Inf while the other instances are unaffected.  Read `info`
- * after synchronising the stream.
+ * was not (the smallest such step among those met), saturated at INT32_MAX
+ * for steps beyond it; that instance's outputs are then NaN or Inf while the
+ * other instances are unaffected.  Read `info` after synchronising the stream.
  */
 #ifndef SMNN_H_
 #define SMNN_H_
@@ -103,7 +103,8 @@ typedef struct {
   const int64_t* steps;   /* HOST array [N] of T_i >= 1, or NULL: all T_i = steps_uniform */
   int64_t steps_uniform;
   int32_t mode;           /* smnn_mode */
-  int32_t refine_steps;   /* refinement steps in the refined modes, 0..2; -1: default (1) */
+  int32_t refine_steps;   /* refinement steps in the refined modes, 0..4; -1: default
+                             (2 for SMNN_MODE_FP64_REFINED at order >= 3, else 1) */
   int32_t chunk;          /* nodes per lane at level 0 (time steps; 4, 8 or 16); 0: default for the order and mode */
   int32_t chunk_upper;    /* nodes per lane at the separator levels >= 1; 0: default for the order */
   int32_t block;          /* threads per workgroup (64..256, multiple of 64); 0: 64 */

@@ -180,7 +180,7 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   // the kernels index the initial values with 32-bit offsets
   if (d->n_inst * d->n_init > INT32_MAX / std::max(1, d->init_points)) return SMNN_ERR_INVALID_ARG;
   if (d->mode < SMNN_MODE_FP64 || d->mode > SMNN_MODE_FP32_REFINED) return SMNN_ERR_INVALID_ARG;
-  if (d->refine_steps < -1 || d->refine_steps > 2) return SMNN_ERR_INVALID_ARG;
+  if (d->refine_steps < -1 || d->refine_steps > 4) return SMNN_ERR_INVALID_ARG;
   if (d->block < 0 || d->block > 256 || d->block % 64 != 0) return SMNN_ERR_INVALID_ARG;
   if (d->max_blocks < 0) return SMNN_ERR_INVALID_ARG;
   const int K = d->order + 1;
@@ -202,7 +202,12 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   p->n_init = d->n_init;
   p->t_init = d->init_points > 0 ? d->init_points : 1;
   p->mode = d->mode;
-  p->refine = d->mode == SMNN_MODE_FP64 ? 0 : (d->refine_steps < 0 ? 1 : d->refine_steps);
+  // Default refinement: each step contracts the error by about cond(M) 2^-53.
+  // Block size >= 4 (order >= 3) meets cond(M) ~ 1e13 at h ~ 0.01, where one
+  // step leaves ~1e-8 in FP64 I/O, so the double modes take two there.
+  p->refine = d->mode == SMNN_MODE_FP64 ? 0
+              : d->refine_steps >= 0 ? d->refine_steps
+              : (K >= 4 && d->mode == SMNN_MODE_FP64_REFINED) ? 2 : 1;
   p->L0 = L0;
   p->L1 = L1;
   p->N = d->n_inst;

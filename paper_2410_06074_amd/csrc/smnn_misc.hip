@@ -41,7 +41,8 @@ __global__ void k_info_init(uint32_t* info, int64_t N) {
 
 __global__ void k_info_finalize(const uint32_t* ws, int32_t* info, int64_t N) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < N) info[i] = ws[i] == 0xFFFFFFFFu ? 0 : static_cast<int32_t>(ws[i]);
+  // 1 + the failing step, saturated at INT32_MAX for steps beyond it
+  if (i < N) info[i] = ws[i] == 0xFFFFFFFFu ? 0 : static_cast<int32_t>(ws[i] > 0x7FFFFFFFu ? 0x7FFFFFFFu : ws[i]);
 }
 
 }  // namespace

@@ -1,25 +1,58 @@
 """Shared helpers of the GPU parity tests: run the HIP path through the C-ABI
-(paper_2410_06074_amd.Plan) on seeded inputs and compare with the oracle."""
+(paper_2410_06074_amd.Plan) on seeded inputs and compare with the oracle.
+
+Reference.  The banded oracle computed in __float128 (``banded.grad(...,
+quad=True)``): the least-squares solution, adjoint and gradients of the
+double inputs rounded once to double (pinned bit-for-bit to the rational
+oracle in tests/test_oracle_exact.py).  Unlike a double-precision oracle it
+carries no error of its own at any conditioning met here, so what a metric
+shows is the HIP path's error.
+
+Pass criteria, per instance (the mode's working precision u_work = 2^-53 for
+the double modes, 2^-24 for float I/O):
+  P1  backward error of y for the normal equations of Eq. 9, evaluated row by
+      row in __float128 (``banded.backward_error``), for every instance
+      whatever its conditioning:
+        normwise ||beta - M y||_inf / (||M||_inf ||y||_inf + ||beta||_inf)
+            <= 50 u_work in every mode (what a backward-stable SPD solve of
+            the normal equations guarantees), except the plain fp64 mode at
+            order >= 3, where it is printed, not asserted: there the
+            partitioned elimination's separator Schur complements lose up
+            to ~150 u (the sequential block Cholesky of the same matrices
+            stays below 1 u), and refinement is what restores it;
+        row-scaled ||A^T W (b - A y)||_inf / || |A|^T W (|A||y| + |b|) ||_inf
+            <= 50 u_work in the refined modes (refinement with a row-wise
+            residual makes the solve backward stable row by row; the plain
+            normal-equation solve is not, and reaches ~750 u at order 3).
+  P2  forward error of y:
+        fp64r  <= 1e-10 per derivative order, both as a relative 2-norm
+               (``y``) and as max |y - y*| / max |y*| (``y_el``), where
+               cond(M) <= 1e14;
+        fp32r  <= 1e-4, same metrics, where cond(M) <= 1e10 (against the
+               oracle on the same float-rounded inputs);
+        fp64   <= max(1e-13, 2 cond(M) 2^-52) for the instance's whole
+               vector, as a relative 2-norm (``y_nw``) and as max |y - y*| /
+               max |y*| (``y_iel``): the forward bound of a backward-stable
+               solve, ~cond(M) u for the normwise error.  (Per order, an
+               order whose values are small against the others' carries a
+               larger share; those columns are printed, not asserted.)
+      Instances above the thresholds are reported, not asserted.
+  Gradients: term-magnitude-scaled error (tests/metrics.py) <= 1e-10 (fp64r),
+      1e-5 (fp32r), max(1e-10, 2 cond(M) 2^-52) (fp64), under the same
+      thresholds; raw relative errors are printed beside them.
+"""
 import numpy as np
 
+from oracle import banded
 from tests import metrics
 
 MODES = ("fp64", "fp64r", "fp32r")
-
-# Tolerances (relative 2-norm error per instance and derivative order).
-#  fp64r: the stated FP64 target.
-#  fp32r: the stated FP32+refinement target; measured against the oracle run on
-#         the same float32-rounded inputs.
-#  fp64 : the paper's single normal-equation solve; its error is bounded by
-#         about c cond(M) * 2^-53, and cond(M) ~ 1.2e9 for the Gaussian
-#         configurations (estimated per instance by oracle.banded.cond), so it
-#         is held to 10 * cond(M) * 2^-53 (floor 1e-12) instead of 1e-10.
+EPS = float(np.finfo(np.float64).eps)           # 2^-52
+U_WORK = {"fp64": 2.0 ** -53, "fp64r": 2.0 ** -53, "fp32r": 2.0 ** -24}
+KAPPA_P2 = {"fp64r": 1e14, "fp32r": 1e10, "fp64": np.inf}
 Y_TOL = {"fp64r": 1e-10, "fp32r": 1e-4}
-# Gradients: term-magnitude-scaled error (tests/metrics.py); the refined FP64
-# adjoint leaves ~1e-15, float32 outputs ~1e-7, and the plain FP64 adjoint
-# carries the same cond(M) * 2^-53 bound as its solution (du0 = w_i^2 lam_1
-# has no cancellation, so it shows the adjoint's own error).
 G_TOL = {"fp64r": 1e-10, "fp32r": 1e-5}
+GRADS = ("dc", "dd", "ds", "du0", "dw")
 
 
 def dtype_for(mode):
@@ -63,6 +96,11 @@ def run(bt, mode, gy=None, chunk=0, block=0, max_blocks=0, refine_steps=-1, devi
     return out
 
 
+def reference(bt, gy):
+    """The __float128 oracle's y, lam and gradients for dl/dy = gy."""
+    return banded.grad(bt, gy, quad=True)
+
+
 def loss_gradient(y, k):
     """dl/dy of l = sum_t y_{t,0}^2 (the loss of the full-size configurations)."""
     g = np.zeros((len(y), k))
@@ -70,40 +108,99 @@ def loss_gradient(y, k):
     return g
 
 
+def _el(x, ref, k):
+    """max over derivative orders of max_t |x - ref| / max_t |ref|."""
+    x = np.asarray(x, dtype=np.float64).reshape(-1, k)
+    ref = np.asarray(ref, dtype=np.float64).reshape(-1, k)
+    out = 0.0
+    for r in range(k):
+        den = np.abs(ref[:, r]).max()
+        out = max(out, float(np.abs(x[:, r] - ref[:, r]).max() / den) if den > 0 else float(np.abs(x[:, r]).max()))
+    return out
+
+
+def _raw(x, ref):
+    x = np.asarray(x, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    den = np.abs(ref).max()
+    nrm = np.linalg.norm(ref)
+    if den == 0:
+        return float(np.abs(x).max()), float(np.abs(x).max())
+    return float(np.linalg.norm(x - ref) / nrm), float(np.abs(x - ref).max() / den)
+
+
 def compare(bt, out, ref, idx, ref_off=None):
-    """Worst y error and worst gradient errors over the instances idx.
-    ref holds oracle arrays for the instances idx (packed with ref_off) or for
-    all instances (ref_off None)."""
+    """Per-instance metrics over the instances idx (dict of arrays, one entry
+    per instance of idx).  ref holds oracle arrays for the instances idx
+    (packed with ref_off) or for all instances (ref_off None)."""
     o = bt.offsets
-    worst = {"y": 0.0}
+    sub = bt.subset(list(idx))
+    m = {"y": [], "y_el": [], "y_nw": [], "y_iel": []}
+    ys = []
     for j, i in enumerate(idx):
         sl = slice(o[i], o[i + 1])
         rs = slice(ref_off[j], ref_off[j + 1]) if ref_off is not None else sl
         ri = j if ref_off is not None else i
-        worst["y"] = max(worst["y"], max(metrics.rel_by_order(out["y"][sl], ref["y"][rs], bt.k)))
+        ys.append(out["y"][sl])
+        m["y"].append(max(metrics.rel_by_order(out["y"][sl], ref["y"][rs], bt.k)))
+        m["y_el"].append(_el(out["y"][sl], ref["y"][rs], bt.k))
+        nw, iel = _raw(out["y"][sl], ref["y"][rs])
+        m["y_nw"].append(nw)
+        m["y_iel"].append(iel)
         if "dc" in out and "dc" in ref:
             c, d, s, u0, w = bt.instance(i)
             sc = metrics.grad_scales(c, d, s, u0, w, ref["y"][rs], ref["lam"][rs])
-            for key in ("dc", "dd", "ds"):
-                worst[key] = max(worst.get(key, 0.0), metrics.grad_error(out[key][sl], ref[key][rs], sc[key]))
-                den = np.linalg.norm(ref[key][rs])
-                if den > 0:
-                    worst[key + "_raw"] = max(worst.get(key + "_raw", 0.0),
-                                              float(np.linalg.norm(out[key][sl] - ref[key][rs]) / den))
-            for key in ("du0", "dw"):
-                if np.size(ref[key][ri]) == 0:    # no initial rows (n_init = 0)
+            for key in GRADS:
+                got, want = (out[key][sl], ref[key][rs]) if key in ("dc", "dd", "ds") else (out[key][i], ref[key][ri])
+                if np.size(want) == 0:             # no initial rows (n_init = 0)
                     continue
-                worst[key] = max(worst.get(key, 0.0), metrics.grad_error(out[key][i], ref[key][ri], sc[key]))
-    return worst
+                m.setdefault(key, []).append(metrics.grad_error(got, want, sc[key]))
+                if key != "dw":     # a sum over all rows whose exact value may be ~0
+                    raw, raw_el = _raw(got, want)
+                    m.setdefault(key + "_raw", []).append(raw)
+                    m.setdefault(key + "_el", []).append(raw_el)
+    yall = np.concatenate(ys) if ys else np.zeros((0, bt.k))
+    m["eta"] = list(banded.backward_error(sub, yall))
+    m["eta_n"] = list(banded.backward_error(sub, yall, normwise=True))
+    return {k: np.asarray(v, dtype=np.float64) for k, v in m.items()}
 
 
-def g_tolerance(mode, kappa):
-    if mode == "fp64":
-        return max(1e-10, 10.0 * kappa * np.finfo(np.float64).eps)
-    return G_TOL[mode]
+def summary(m):
+    """One line: worst value of every metric."""
+    return " ".join("%s=%.1e" % (k, float(np.max(v))) for k, v in m.items() if np.size(v))
 
 
 def y_tolerance(mode, kappa):
     if mode == "fp64":
-        return max(1e-12, 10.0 * kappa * np.finfo(np.float64).eps)
+        return max(1e-13, 2.0 * kappa * EPS)
     return Y_TOL[mode]
+
+
+def g_tolerance(mode, kappa):
+    if mode == "fp64":
+        return max(1e-10, 2.0 * kappa * EPS)
+    return G_TOL[mode]
+
+
+def check(mode, m, kappa, order, grads=True):
+    """Assert P1 on every instance and P2 (and the gradient bounds) on the
+    instances whose cond(M) is within the mode's threshold."""
+    kappa = np.broadcast_to(np.asarray(kappa, dtype=np.float64), m["eta"].shape)
+    p1 = 50.0 * U_WORK[mode]
+    if mode != "fp64" or order <= 2:
+        bad = np.nonzero(m["eta_n"] > p1)[0]
+        assert bad.size == 0, ("P1 normwise backward error", m["eta_n"][bad], kappa[bad])
+    if mode != "fp64":
+        bad = np.nonzero(m["eta"] > p1)[0]
+        assert bad.size == 0, ("P1 row-scaled backward error", m["eta"][bad], kappa[bad])
+    ykeys = ("y_nw", "y_iel") if mode == "fp64" else ("y", "y_el")
+    for j in range(len(kappa)):
+        if kappa[j] > KAPPA_P2[mode]:
+            continue
+        ty, tg = y_tolerance(mode, kappa[j]), g_tolerance(mode, kappa[j])
+        for key in ykeys:
+            assert m[key][j] <= ty, ("P2", key, j, m[key][j], kappa[j])
+        if grads:
+            for key in GRADS:
+                if key in m:
+                    assert m[key][j] <= tg, ("gradient", key, j, m[key][j], kappa[j])

@@ -57,7 +57,7 @@ def _desc(**kw):
 
 
 @pytest.mark.parametrize("field,value", [("order", 0), ("order", 5), ("n_init", 4), ("n_init", -1),
-                                         ("n_inst", 0), ("steps_uniform", 0), ("mode", 3), ("refine_steps", 3),
+                                         ("n_inst", 0), ("steps_uniform", 0), ("mode", 3), ("refine_steps", 5),
                                          ("block", 96), ("block", 512), ("max_blocks", -1),
                                          ("init_points", -1), ("init_points", 1 << 29)])
 def test_invalid_plan_descriptions_rejected_on_host(field, value):

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import banded, dense
+from tests import fixtures as golden
 from tests import gpu_helpers as H
 from workloads import config, gaussian_batch, polynomial_batch
 
@@ -32,12 +33,34 @@ def test_c0_forward_matches_dense_definition(mode):
     bt = H.io_batch(config("c0"), mode)
     out = H.run(bt, mode)
     c, d, s, u0, w = bt.instance(0)
-    ref = dense.solve(c, d, s, u0, w)
-    kappa = float(banded.cond(bt)[0])
-    err = max(H.metrics.rel_by_order(out["y"], ref, bt.k))
-    _print("c0", mode, "err %.2e kappa %.2e" % (err, kappa))
-    assert err <= H.y_tolerance(mode, kappa)
+    ref = {"y": dense.solve(c, d, s, u0, w)}
+    kappa = banded.cond(bt)
+    m = H.compare(bt, out, ref, [0])
+    _print("c0", mode, H.summary(m), "kappa %.2e" % kappa[0])
+    H.check(mode, m, kappa, bt.R, grads=False)
     assert out["info"].tolist() == [0]
+
+
+# --------------------------------------------------- exact rational fixtures
+@pytest.mark.parametrize("case", range(2))
+def test_exact_fixture_elementwise(case):
+    # T = 5, 9, 17 with level-0 chunks of 4 and separator chunks of 4: one,
+    # two and four separators, and a second partition level at T = 17.  The
+    # expected values are the rational oracle's, rounded once to double.
+    bt, gy, want = golden.load_exact(case)
+    out = H.run(bt, "fp64r", gy, chunk=4, chunk_upper=4)
+    assert (out["info"] == 0).all()
+    o = bt.offsets
+    worst = {}
+    for i in range(bt.n_inst):
+        sl = slice(o[i], o[i + 1])
+        for key in ("y", "dc", "dd", "ds"):
+            worst[key] = max(worst.get(key, 0.0), H._raw(out[key][sl], want[key][sl])[1])
+        for key in ("du0", "dw"):
+            worst[key] = max(worst.get(key, 0.0), H._raw(out[key][i], want[key][i])[1])
+    _print("exact fixture R=%d T=%s" % (bt.R, bt.T.tolist()), " ".join("%s=%.1e" % kv for kv in worst.items()))
+    for key, v in worst.items():
+        assert v <= 1e-10, key
 
 
 # --------------------------------------------- ragged edge lengths, all modes
@@ -58,49 +81,55 @@ def test_ragged_lengths_forward_and_gradients(R, chunk, upper, mode):
     gy = np.random.default_rng(R).standard_normal(bt.c.shape)
     if mode == "fp32r":
         gy = gy.astype(np.float32).astype(np.float64)
-    ref = banded.grad(bt, gy)
+    ref = H.reference(bt, gy)
     out = H.run(bt, mode, gy, chunk=chunk, chunk_upper=upper)
-    worst = H.compare(bt, out, ref, range(bt.n_inst))
-    kappa = banded.cond(bt).max()
-    _print("ragged R=%d L=%d/%d %s" % (R, chunk, upper, mode), " ".join("%s=%.1e" % kv for kv in worst.items()),
-           "kappa<=%.1e" % kappa)
-    if R <= 2:
-        assert worst["y"] <= H.y_tolerance(mode, kappa)
-    else:
-        # R = 3 at h ~ 0.01 has cond(M) ~ 1e12..1e14: the oracle's own error is
-        # ~cond(A) u, so compare at the accuracy both sides resolve.
-        assert worst["y"] <= max(H.y_tolerance(mode, kappa), 1e4 * np.sqrt(kappa) * np.finfo(float).eps)
-    resolve = 1e4 * np.sqrt(kappa) * np.finfo(float).eps if R >= 3 else 0.0
-    for key in ("dc", "dd", "ds", "du0", "dw"):
-        assert worst[key] <= max(H.g_tolerance(mode, kappa), resolve), key
+    m = H.compare(bt, out, ref, range(bt.n_inst))
+    kappa = banded.cond(bt)
+    _print("ragged R=%d L=%d/%d %s" % (R, chunk, upper, mode), H.summary(m), "kappa<=%.1e" % kappa.max())
+    H.check(mode, m, kappa, bt.R)
     assert (out["info"] == 0).all()
 
 
 # ------------------------------------------------------- full-size, sampled
-def _sampled(name, mode, idx, n_inst=None, T=None, loss_from_oracle=True):
+def _sampled(name, mode, idx, n_inst=None, T=None, quad=True, eta_idx=None):
+    """Run a full-size configuration with dl/dy = the loss gradient on the
+    sampled instances idx (zero elsewhere); compare idx with the oracle and
+    evaluate the backward error of y on the instances eta_idx (default all)."""
     bt = H.io_batch(config(name, n_inst=n_inst, T=T), mode)
     sub = bt.subset(idx)
-    y_ref = banded.solve(sub)
+    y_ref = banded.solve(sub, quad=quad)
     g_sub = H.loss_gradient(y_ref, bt.k)
-    ref = banded.grad(sub, g_sub)
+    ref = banded.grad(sub, g_sub, quad=quad)
     gy = np.zeros_like(bt.c)
     o, so = bt.offsets, sub.offsets
     for j, i in enumerate(idx):
         gy[o[i]:o[i + 1]] = g_sub[so[j]:so[j + 1]]
     out = H.run(bt, mode, gy)
-    worst = H.compare(bt, out, ref, idx, ref_off=so)
+    m = H.compare(bt, out, ref, idx, ref_off=so)
     kappa = banded.cond(sub)
-    return bt, out, worst, kappa
+    eta_idx = range(bt.n_inst) if eta_idx is None else eta_idx
+    esub = bt.subset(list(eta_idx))
+    rows = np.concatenate([np.arange(o[i], o[i + 1]) for i in eta_idx])
+    eta_all = (banded.backward_error(esub, out["y"][rows]), banded.backward_error(esub, out["y"][rows], normwise=True))
+    return bt, out, m, kappa, eta_all
+
+
+def _report(tag, m, kappa, eta_all, mode):
+    eta_c, eta_n = eta_all
+    _print(tag, H.summary(m), "kappa", " ".join("%.1e" % k for k in kappa),
+           "| over %d instances: eta_n max %.1e, eta max %.1e median %.1e" % (
+               len(eta_c), eta_n.max(), eta_c.max(), np.median(eta_c)))
+    assert eta_n.max() <= 50.0 * H.U_WORK[mode], "P1 normwise backward error"
+    if mode != "fp64":
+        assert eta_c.max() <= 50.0 * H.U_WORK[mode], "P1 row-scaled backward error"
 
 
 @pytest.mark.parametrize("mode", H.MODES)
 def test_c1_full_batch_sampled(mode):
     idx = [0, 1, 511, 1024, 1535]
-    bt, out, worst, kappa = _sampled("c1", mode, idx)
-    _print("c1", mode, " ".join("%s=%.1e" % kv for kv in worst.items()), "kappa<=%.1e" % kappa.max())
-    assert worst["y"] <= H.y_tolerance(mode, kappa.max())
-    for key in ("dc", "dd", "ds", "du0", "dw"):
-        assert worst[key] <= H.g_tolerance(mode, kappa.max()), key
+    bt, out, m, kappa, eta_all = _sampled("c1", mode, idx)
+    _report("c1 " + mode, m, kappa, eta_all, mode)
+    H.check(mode, m, kappa, bt.R)
     assert (out["info"] == 0).all()
     assert np.isfinite(out["y"]).all()
 
@@ -108,40 +137,43 @@ def test_c1_full_batch_sampled(mode):
 @pytest.mark.parametrize("mode", H.MODES)
 def test_headline_t10k_sampled(mode):
     idx = [0, 767, 1535]
-    bt, out, worst, kappa = _sampled("h", mode, idx)
-    _print("h", mode, " ".join("%s=%.1e" % kv for kv in worst.items()), "kappa<=%.1e" % kappa.max())
-    assert worst["y"] <= H.y_tolerance(mode, kappa.max())
-    for key in ("dc", "dd", "ds", "du0", "dw"):
-        assert worst[key] <= H.g_tolerance(mode, kappa.max()), key
+    bt, out, m, kappa, eta_all = _sampled("h", mode, idx)
+    _report("h " + mode, m, kappa, eta_all, mode)
+    H.check(mode, m, kappa, bt.R)
     assert (out["info"] == 0).all()
 
 
 def test_c2_fp32r_sampled_reports_conditioning():
-    # AR(1) coefficients with h = 1/365: cond(M) ~ 1e11..1e13.  fp32r is held
-    # to 1e-4 where cond(M) <= 1e14 (one FP64-residual refinement step
-    # contracts by ~cond(M) u); errors above that are reported, not asserted.
-    idx = [0, 16383, 32767]
-    bt, out, worst, kappa = _sampled("c2", "fp32r", idx, n_inst=32768)
-    _print("c2 fp32r", " ".join("%s=%.1e" % kv for kv in worst.items()), "kappa", kappa)
-    if kappa.max() <= 1e14:
-        assert worst["y"] <= 1e-4
+    # AR(1) coefficients with h = 1/365: cond(M) ~ 1e12 (above the fp32r
+    # threshold, so P2 is reported; P1 holds on every instance checked)
+    idx = [0, 5000, 16383, 32767]
+    bt, out, m, kappa, eta_all = _sampled("c2", "fp32r", idx, n_inst=32768, eta_idx=range(0, 32768, 8))
+    _report("c2 fp32r", m, kappa, eta_all, "fp32r")
+    H.check("fp32r", m, kappa, bt.R)
     assert (out["info"] == 0).all()
 
 
-def test_c3_ragged_r3_sampled():
-    idx = [0, 1, 1000, 2047]
-    bt, out, worst, kappa = _sampled("c3", "fp32r", idx)
-    _print("c3 fp32r T=%s" % bt.T[idx].tolist(), " ".join("%s=%.1e" % kv for kv in worst.items()),
-           "kappa", ["%.1e" % k for k in kappa])
-    assert np.isfinite(out["y"]).all()
+@pytest.mark.parametrize("mode", ["fp32r", "fp64r"])
+def test_c3_ragged_r3_sampled(mode):
+    # R = 3, log-uniform weights: cond(M) 1e13..1e16 (beyond the fp32r
+    # threshold everywhere, around the fp64r one); fp64r on the same inputs is
+    # the accuracy reference the fp32r form is compared with
+    cfg = config("c3")
+    order = np.argsort(cfg.T)
+    idx = sorted({0, 1, 1000, 2047, int(order[0]), int(order[1]), int(order[-1]), int(order[-2])})
+    bt, out, m, kappa, eta_all = _sampled("c3", mode, idx)
+    _report("c3 %s T=%s" % (mode, bt.T[idx].tolist()), m, kappa, eta_all, mode)
+    H.check(mode, m, kappa, bt.R)
     assert (out["info"] == 0).all()
 
 
 def test_c4_long_sequence_sampled():
+    # T = 1e6: the double-precision oracle is the reference here (its own
+    # error, ~1e-9, is far below the fp32r target); P1 in __float128 on all 32
     idx = [0, 31]
-    bt, out, worst, kappa = _sampled("c4", "fp32r", idx)
-    _print("c4 fp32r", " ".join("%s=%.1e" % kv for kv in worst.items()), "kappa", kappa)
-    assert worst["y"] <= 1e-4
+    bt, out, m, kappa, eta_all = _sampled("c4", "fp32r", idx, quad=False)
+    _report("c4 fp32r", m, kappa, eta_all, "fp32r")
+    H.check("fp32r", m, kappa, bt.R)
     assert (out["info"] == 0).all()
 
 
@@ -178,22 +210,13 @@ def test_initial_row_counts(n_init):
     T = [1, 5, 64, 333, 1000] if n_init >= 2 else [5, 64, 333, 1000]
     bt = gaussian_batch(len(T), T, R=2, seed=40 + n_init, n_init=n_init, weights=(1.1, 0.7, 1.3))
     gy = np.random.default_rng(n_init).standard_normal(bt.c.shape)
-    ref = banded.grad(bt, gy)
-    kappa = banded.cond(bt).max()
+    ref = H.reference(bt, gy)
+    kappa = banded.cond(bt)
     out = H.run(bt, "fp64r", gy)
-    worst = H.compare(bt, out, ref, range(bt.n_inst))
-    _print("n_init=%d" % n_init, " ".join("%s=%.1e" % kv for kv in worst.items()), "kappa<=%.1e" % kappa)
+    m = H.compare(bt, out, ref, range(bt.n_inst))
+    _print("n_init=%d" % n_init, H.summary(m), "kappa<=%.1e" % kappa.max())
     assert (out["info"] == 0).all()
-    assert worst["y"] <= H.y_tolerance("fp64r", kappa)
-    for key in ("dc", "dd", "ds", "dw"):
-        assert worst[key] <= H.g_tolerance("fp64r", kappa), key
-    if n_init > 0:
-        # with one initial row the T = 5 instance has cond(M) ~ 4e9 and du0
-        # takes the whole of it: the oracle's banded and dense adjoints differ
-        # there by ~2e-9 relative, so du0 is compared at the oracle's own
-        # forward-error bound ~cond u
-        resolve = 10.0 * kappa * np.finfo(float).eps
-        assert worst["du0"] <= max(H.g_tolerance("fp64r", kappa), resolve)
+    H.check("fp64r", m, kappa, bt.R)
 
 
 @pytest.mark.parametrize("mode", ["fp64", "fp64r", "fp32r"])
@@ -208,17 +231,14 @@ def test_several_initial_points(mode, t_init, n_init):
     gy = np.random.default_rng(t_init).standard_normal(bt.c.shape)
     if mode == "fp32r":
         gy = gy.astype(np.float32).astype(np.float64)
-    ref = banded.grad(bt, gy)
-    kappa = banded.cond(bt).max()
+    ref = H.reference(bt, gy)
+    kappa = banded.cond(bt)
     out = H.run(bt, mode, gy)
     assert out["plan"].init_points == t_init
-    worst = H.compare(bt, out, ref, range(bt.n_inst))
-    _print("init points %d x %d %s" % (t_init, n_init, mode), " ".join("%s=%.1e" % kv for kv in worst.items()),
-           "kappa<=%.1e" % kappa)
+    m = H.compare(bt, out, ref, range(bt.n_inst))
+    _print("init points %d x %d %s" % (t_init, n_init, mode), H.summary(m), "kappa<=%.1e" % kappa.max())
     assert (out["info"] == 0).all()
-    assert worst["y"] <= H.y_tolerance(mode, kappa)
-    for key in ("dc", "dd", "ds", "du0", "dw"):
-        assert worst[key] <= H.g_tolerance(mode, kappa), key
+    H.check(mode, m, kappa, bt.R)
     du0 = out["du0"].reshape(bt.n_inst, t_init, n_init)
     for i, Ti in enumerate(T):
         assert np.all(du0[i, Ti:] == 0.0)
@@ -234,16 +254,14 @@ def test_upper_levels_in_one_launch(mode):
         gy = np.random.default_rng(top).standard_normal(bt.c.shape)
         if mode == "fp32r":
             gy = gy.astype(np.float32).astype(np.float64)
-        ref = banded.grad(bt, gy)
-        kappa = banded.cond(bt).max()
+        ref = H.reference(bt, gy)
+        kappa = banded.cond(bt)
         out = H.run(bt, mode, gy, chunk=4, chunk_upper=4)
         assert out["plan"].top_level == top
-        worst = H.compare(bt, out, ref, range(bt.n_inst))
-        _print("upper levels %s top=%d" % (mode, top), " ".join("%s=%.1e" % kv for kv in worst.items()))
+        m = H.compare(bt, out, ref, range(bt.n_inst))
+        _print("upper levels %s top=%d" % (mode, top), H.summary(m))
         assert (out["info"] == 0).all()
-        assert worst["y"] <= H.y_tolerance(mode, kappa)
-        for key in ("dc", "dd", "ds", "du0", "dw"):
-            assert worst[key] <= H.g_tolerance(mode, kappa), key
+        H.check(mode, m, kappa, bt.R)
 
 
 def test_failure_reported_per_instance_and_isolated():
@@ -286,19 +304,21 @@ def test_refinement_steps(mode):
         gy = np.random.default_rng(5).standard_normal(bt.c.shape)
         if mode == "fp32r":
             gy = gy.astype(np.float32).astype(np.float64)
-        ref = banded.grad(bt, gy)
-        kappa = banded.cond(bt).max()
+        ref = H.reference(bt, gy)
+        kappa = banded.cond(bt)
         errs = []
         for steps in (0, 1, 2):
             out = H.run(bt, mode, gy, chunk=4, chunk_upper=8, refine_steps=steps)
             assert out["plan"].refine_steps == steps
-            worst = H.compare(bt, out, ref, range(bt.n_inst))
-            errs.append(worst)
-            _print("refine %s T=%s steps=%d" % (mode, T, steps), " ".join("%s=%.1e" % kv for kv in worst.items()))
+            m = H.compare(bt, out, ref, range(bt.n_inst))
+            errs.append(m)
+            _print("refine %s T=%s steps=%d" % (mode, T, steps), H.summary(m))
             if steps == 0:
-                assert worst["y"] <= H.y_tolerance("fp64", kappa) if mode == "fp64r" else worst["y"] <= 1e-3
+                # no refinement: the plain FP64 solve's bound (fp32r: its output rounding on top)
+                if mode == "fp64r":
+                    H.check("fp64", m, kappa, bt.R)
+                else:
+                    assert m["y"].max() <= 1e-3
             else:
-                assert worst["y"] <= H.y_tolerance(mode, kappa)
-                for key in ("dc", "dd", "ds", "du0", "dw"):
-                    assert worst[key] <= H.g_tolerance(mode, kappa), key
-        assert errs[2]["y"] <= max(2 * errs[1]["y"], 1e-13)
+                H.check(mode, m, kappa, bt.R)
+        assert errs[2]["y"].max() <= max(2 * errs[1]["y"].max(), 1e-13)

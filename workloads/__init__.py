@@ -39,10 +39,18 @@ class Batch:
     w: np.ndarray          # [N, 3]
     name: str = ""
     t_init: int = 1        # time points carrying initial values
+    V: int = 1             # variables per instance (Sec. 3.1)
+    Q: int = 1             # governing equations per time point
+    wrow: dict | None = None   # per-row weights {"wg": [S, Q], "wi": [N, t_init*V*n_init], "ws": [S]}
 
     @property
     def n_inst(self) -> int:
         return int(self.T.shape[0])
+
+    @property
+    def block(self) -> int:
+        """Unknowns per time point, V (R+1)."""
+        return self.V * (self.R + 1)
 
     @property
     def k(self) -> int:
@@ -60,7 +68,9 @@ class Batch:
 
     def instance(self, i: int):
         """(c, b, h, u0, w) of instance i as float64 views/copies; u0 is
-        [n_init] when t_init = 1, else [t_init, n_init]."""
+        [n_init] when t_init = 1, else [t_init, n_init].  Scalar weights and
+        V = Q = 1 only (see ``instance_general``)."""
+        assert self.V == 1 and self.Q == 1 and self.wrow is None
         o = self.offsets
         s, e = int(o[i]), int(o[i + 1])
         return (np.asarray(self.c[s:e], dtype=np.float64),
@@ -70,20 +80,44 @@ class Batch:
                  else np.asarray(self.u0[i], dtype=np.float64).reshape(self.t_init, self.n_init)),
                 np.asarray(self.w[i], dtype=np.float64))
 
+    def instance_general(self, i: int):
+        """(c [T, Q, V(R+1)], d [T, Q], s [T], u [t_init, V, n_init],
+        wg [T, Q], wi [t_init, V, n_init], ws [T]) of instance i, float64,
+        with scalar weights expanded to their rows."""
+        o = self.offsets
+        s, e = int(o[i]), int(o[i + 1])
+        T, K = e - s, self.block
+        c = np.asarray(self.c[s:e], dtype=np.float64).reshape(T, self.Q, K)
+        d = np.asarray(self.b[s:e], dtype=np.float64).reshape(T, self.Q)
+        h = np.asarray(self.h[s:e], dtype=np.float64).reshape(T)
+        u = np.asarray(self.u0[i], dtype=np.float64).reshape(self.t_init, self.V, self.n_init)
+        if self.wrow is None:
+            w = np.asarray(self.w[i], dtype=np.float64)
+            wg, wi, ws = np.full((T, self.Q), w[0]), np.full(u.shape, w[1]), np.full(T, w[2])
+        else:
+            wg = np.asarray(self.wrow["wg"][s:e], dtype=np.float64).reshape(T, self.Q)
+            wi = np.asarray(self.wrow["wi"][i], dtype=np.float64).reshape(u.shape)
+            ws = np.asarray(self.wrow["ws"][s:e], dtype=np.float64).reshape(T)
+        return c, d, h, u, wg, wi, ws
+
     def astype(self, dtype) -> "Batch":
+        wrow = None if self.wrow is None else {k: v.astype(dtype) for k, v in self.wrow.items()}
         return dataclasses.replace(
             self, c=self.c.astype(dtype), b=self.b.astype(dtype),
             h=self.h.astype(dtype), u0=self.u0.astype(dtype),
-            w=self.w.astype(dtype))
+            w=self.w.astype(dtype), wrow=wrow)
 
     def subset(self, idx) -> "Batch":
         """A new batch holding the instances in ``idx`` (in that order)."""
         o = self.offsets
+        idx = list(idx)
         rows = np.concatenate([np.arange(o[i], o[i + 1]) for i in idx]) if len(idx) else np.zeros(0, np.int64)
-        return Batch(R=self.R, n_init=self.n_init, T=self.T[list(idx)].copy(),
+        wrow = None if self.wrow is None else {"wg": self.wrow["wg"][rows].copy(), "ws": self.wrow["ws"][rows].copy(),
+                                               "wi": self.wrow["wi"][idx].copy()}
+        return Batch(R=self.R, n_init=self.n_init, T=self.T[idx].copy(),
                      c=self.c[rows].copy(), b=self.b[rows].copy(), h=self.h[rows].copy(),
-                     u0=self.u0[list(idx)].copy(), w=self.w[list(idx)].copy(),
-                     name=self.name + "[subset]", t_init=self.t_init)
+                     u0=self.u0[idx].copy(), w=self.w[idx].copy(),
+                     name=self.name + "[subset]", t_init=self.t_init, V=self.V, Q=self.Q, wrow=wrow)
 
 
 def _gaussian_c(rng, S, R, scale=1.0):
