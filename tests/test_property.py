@@ -124,12 +124,11 @@ def test_hip_path_matches_oracle(bt):
     kappa = _usable(bt)
     assume(kappa is not None)
     gy = np.random.default_rng(1).standard_normal(bt.c.shape)
-    ref = banded.grad(bt, gy)
+    ref = H.reference(bt, gy)          # the __float128 oracle
     out = H.run(bt, "fp64r", gy)
     assert (out["info"] == 0).all()
     assert backward_error(bt, out["y"]) <= 1e-13
-    worst = H.compare(bt, out, ref, range(bt.n_inst))
-    tol = _lsq_tol(kappa, 1e-10)
-    for key in ("y", "dc", "dd", "ds", "du0", "dw"):
-        if key in worst:
-            assert worst[key] <= tol, key
+    m = H.compare(bt, out, ref, range(bt.n_inst))
+    # P1 on every instance, P2 (1e-10 per order and element by element) and
+    # the gradient bound (1e-10, term-scaled) where cond(M) <= 1e14
+    H.check("fp64r", m, kappa, bt.R)
