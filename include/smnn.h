@@ -160,6 +160,24 @@ smnn_status smnn_backward(const smnn_plan* plan, const void* c, const void* b, c
                           void* dc, void* db, void* dh, void* du0, void* dw, void* workspace,
                           size_t workspace_bytes, int32_t* info, void* stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): smnn_forward
+ * with its workspace taken from a static device array of the library
+ * (SMNN_NOALLOC_WORKSPACE_MAX bytes, held on every device the library runs
+ * on until the process ends) instead of a caller buffer.  Same kernels,
+ * arguments and results as smnn_forward.  Returns SMNN_ERR_WORKSPACE when
+ * the plan's workspace (smnn_plan_sizes) exceeds SMNN_NOALLOC_WORKSPACE_MAX,
+ * SMNN_ERR_HIP if the array's device address cannot be obtained.  The call
+ * itself allocates nothing (the address lookup happens once per device, at
+ * the first call there).  Every call on a device shares that device's array:
+ * calls that overlap in time on one device race and give undefined results;
+ * serialise them (one stream, or events).  Nothing in the array needs to be
+ * cleared between calls: every word a call reads it has written first. */
+#define SMNN_NOALLOC_WORKSPACE_MAX (128u << 20)
+smnn_status smnn_forward_noalloc(const smnn_plan* plan, const void* c, const void* b, const void* h,
+                                 const void* u0, const void* w, void* y, void* factor, size_t factor_bytes,
+                                 int32_t* info, void* stream);
+
 /* Per-launch timing (profiling aid; not for concurrent or captured calls).
  * smnn_trace_enable(plan, n) makes the following smnn_forward/smnn_backward
  * calls on this plan record a hipEvent before and after each kernel launch,

@@ -65,6 +65,8 @@ def lib():
         L.smnn_plan_query.restype = ctypes.c_int64
         L.smnn_forward.argtypes = [vp] * 8 + [sz, vp, sz, vp, vp]
         L.smnn_forward.restype = ctypes.c_int
+        L.smnn_forward_noalloc.argtypes = [vp] * 8 + [sz, vp, vp]
+        L.smnn_forward_noalloc.restype = ctypes.c_int
         L.smnn_backward.argtypes = [vp] * 8 + [sz] + [vp] * 7 + [sz, vp, vp]
         L.smnn_backward.restype = ctypes.c_int
         L.smnn_trace_enable.argtypes = [vp, ctypes.c_int32]

@@ -3,7 +3,7 @@
     python -m paper_2410_06074_amd.build
 
 compiles csrc/smnn_kernels.hip once per block size (K = 2..5) in parallel,
-csrc/smnn_misc.hip and csrc/smnn_api.cpp, and links them into
+csrc/smnn_misc.hip, csrc/smnn_noalloc.hip and csrc/smnn_api.cpp, and links them into
 paper_2410_06074_amd/libsmnn.so.  Objects go to paper_2410_06074_amd/_build/.
 """
 from __future__ import annotations
@@ -49,6 +49,8 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         units.append([hipcc, *COMMON, f"-DSMNN_TU_K={K}", "-c", os.path.join(CSRC, "smnn_kernels.hip"),
                       "-o", os.path.join(BUILD, f"smnn_kernels_k{K}.o")])
     units.append([hipcc, *COMMON, "-c", os.path.join(CSRC, "smnn_misc.hip"), "-o", os.path.join(BUILD, "smnn_misc.o")])
+    units.append([hipcc, *COMMON, "-c", os.path.join(CSRC, "smnn_noalloc.hip"),
+                  "-o", os.path.join(BUILD, "smnn_noalloc.o")])
     units.append([hipcc, *COMMON, "-c", os.path.join(CSRC, "smnn_api.cpp"), "-o", os.path.join(BUILD, "smnn_api.o")])
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_run, units))

@@ -147,6 +147,16 @@ class Plan:
                                         _ptr(factor), factor.numel(), _ptr(workspace), workspace.numel(),
                                         _ptr(info), ctypes.c_void_p(st)), "smnn_forward")
 
+    def forward_noalloc(self, c, b, h, u0, w, y, factor, info=None, stream=None):
+        """Enqueue smnn_forward_noalloc: smnn_forward with the library's static
+        device workspace (plans whose workspace fits it; see include/smnn.h)."""
+        self._check_inputs(c, b, h, u0, w)
+        self._check("y", y, (self.total_steps, self.k))
+        st = torch.cuda.current_stream(c.device).cuda_stream if stream is None else stream
+        _lib.check(self._L.smnn_forward_noalloc(self._h, _ptr(c), _ptr(b), _ptr(h), _ptr(u0), _ptr(w), _ptr(y),
+                                                _ptr(factor), factor.numel(), _ptr(info), ctypes.c_void_p(st)),
+                   "smnn_forward_noalloc")
+
     def backward(self, c, b, h, u0, w, y, factor, gy, dc, db, dh, du0, dw, workspace, info=None, stream=None):
         """Enqueue smnn_backward on `stream` (default: torch's current stream)."""
         self._check_inputs(c, b, h, u0, w)
