@@ -2,20 +2,24 @@
  * smnn.h -- C-ABI of libsmnn: the batched linear-ODE least-squares solve of
  * Scalable Mechanistic Neural Networks (S-MNN), on AMD Instinct MI355X (gfx950).
  *
- * What is solved (Sec. 3.1, Eqs. 4-9; App. A.1-A.2).  An instance is one
- * (batch element, variable) pair with T time points and unknowns
- * y_{t,r}, r = 0..R (the r-th derivative at point t).  Its weighted
- * constraints are
- *   governing (Eq. 4):   sum_r c_{t,r} y_{t,r} = b_t                 weight w_gov
- *   initial   (Eq. 5):   y_{t,r} = u0_{t,r}, t < T_init, r < n_init     weight w_init
+ * What is solved (Sec. 3.1, Eqs. 4-9; App. A.1-A.2).  An instance has T
+ * time points, V variables (commonly one: a (batch element, variable) pair)
+ * and unknowns y_{t,v,r}, r = 0..R (the r-th derivative of variable v at
+ * point t).  Its weighted constraints are
+ *   governing (Eq. 4):   sum_{v,r} c_{t,q,v,r} y_{t,v,r} = b_{t,q},
+ *                        q = 1..Q equations per point       weight w_gov
+ *   initial   (Eq. 5):   y_{t,v,r} = u0_{t,v,r}, t < T_init, r < n_init
+ *                                                             weight w_init
  *                        (T_init = init_points; points past an instance's
  *                        last one carry no row)
- *   smoothness (Eqs. 6-7): forward and backward Taylor expansions between
- *                        points t and t+1 with step h_t, every order
- *                        r = 0..R, each row weighted by w_smooth * h_t^r
- * and the solution is the weighted least-squares minimiser (Eq. 9),
+ *   smoothness (Eqs. 6-7): forward and backward Taylor expansions of every
+ *                        variable between points t and t+1 with step h_t,
+ *                        every order r = 0..R, each row weighted by
+ *                        w_smooth * h_t^r
+ * (the weights are three scalars per instance, or one per row), and the
+ * solution is the weighted least-squares minimiser (Eq. 9),
  *   y = (A^T W A)^{-1} A^T W b.
- * The normal matrix is block tridiagonal with (R+1)x(R+1) blocks (Eq. 10)
+ * The normal matrix is block tridiagonal with V(R+1) x V(R+1) blocks (Eq. 10)
  * and is factored and solved in O(T) by block Cholesky with forward and back
  * substitution (Eqs. 11-13, Alg. 1, 3, 4).  The backward pass solves the
  * adjoint system of Eq. 14, lam = M^{-1} dl/dy, and forms the gradients with
@@ -41,16 +45,29 @@
  * Memory layout (all array pointers are DEVICE pointers).  Per-step arrays
  * are instance-major and time-contiguous: instance i owns rows
  * off[i] .. off[i]+T[i]-1, off = exclusive prefix sum of T, S = sum(T).
- *   c   [S][R+1]  governing coefficients c_{t,r}
- *   b   [S]       governing right-hand side
- *   h   [S]       h[off[i]+t] = step between points t and t+1; the last slot
- *                 of each instance is read by nothing
- *   u0  [N][T_init][n_init]  initial values (point-major per instance)
- *   w   [N][3]    (w_gov, w_init, w_smooth), unsquared, > 0
- *   y   [S][R+1]  solution; gy, dc share this shape; db, dh share b's;
- *                 du0 shares u0's (entries for points past an instance's
- *                 end are written as 0); dw shares w's.
- * For a uniform batch these are contiguous (N, T, R+1), (N, T), ... arrays.
+ * An instance has V variables (default 1) and Q governing equations per
+ * point (default V); K = V (R+1) unknowns per point, variable-major:
+ * unknown v (R+1) + r is derivative r of variable v (App. A.1's y_t).
+ *   c   [S][Q][K]  governing coefficients c_{t,q,v,r}
+ *   b   [S][Q]     governing right-hand sides d_{t,q}
+ *   h   [S]        h[off[i]+t] = step between points t and t+1; the last slot
+ *                  of each instance is read by nothing
+ *   u0  [N][T_init][V][n_init]  initial values (point-major per instance)
+ *   w   scalar weights (row_weights = 0): [N][3] (w_gov, w_init, w_smooth),
+ *       unsquared, > 0, each applied to every row of its kind;
+ *       per-row weights (row_weights = 1), unsquared, > 0, one buffer of
+ *       S Q + N T_init V n_init + S elements: [S][Q] the weight of each
+ *       governing row, then [N][T_init][V][n_init] the weight of each
+ *       initial row, then [S] the weight of the smoothness rows between
+ *       points t and t+1 (every variable and order; the row of order r is
+ *       weighted by that weight times h_t^r), last slot of each instance
+ *       unused (App. A.1's W = diag(w))
+ *   y   [S][K]     solution; gy shares this shape, dc c's, db b's, dh h's;
+ *                  du0 shares u0's (entries for points past an instance's
+ *                  end are written as 0); dw shares w's (per-row weights:
+ *                  the gradient of every row's weight, the unused slots 0).
+ * For a uniform one-variable batch these are contiguous (N, T, R+1),
+ * (N, T), ... arrays.
  *
  * Ownership.  The caller allocates and owns every buffer.  `factor`
  * (smnn_plan_sizes) is written by smnn_forward and read by smnn_backward of
@@ -82,7 +99,7 @@ extern "C" {
 typedef enum {
   SMNN_OK = 0,
   SMNN_ERR_INVALID_ARG = 1, /* bad size, mode, pointer or plan */
-  SMNN_ERR_UNSUPPORTED = 2, /* order / chunk length not compiled in */
+  SMNN_ERR_UNSUPPORTED = 2, /* order, chunk length or instance shape not compiled in */
   SMNN_ERR_WORKSPACE = 3,   /* workspace or factor smaller than required */
   SMNN_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed */
   SMNN_ERR_DEVICE = 5       /* called with another device current than at plan creation */
@@ -97,7 +114,7 @@ typedef enum {
 typedef struct smnn_plan smnn_plan; /* opaque; immutable after creation */
 
 typedef struct {
-  int32_t order;          /* R, 1..4 (block size R+1) */
+  int32_t order;          /* R, 1..4; the block size V (R+1) must be <= 5 */
   int32_t n_init;         /* initial orders fixed at each initial point, 0..R+1 */
   int64_t n_inst;         /* N >= 1 */
   const int64_t* steps;   /* HOST array [N] of T_i >= 1, or NULL: all T_i = steps_uniform */
@@ -111,7 +128,12 @@ typedef struct {
   int32_t max_blocks;     /* >0: persistent grid-stride launch with at most this many
                              workgroups per kernel; 0: one wavefront per tile */
   int32_t init_points;    /* T_init: leading time points with initial values (Eq. 5); 0: 1.
-                             N * T_init * n_init must not exceed INT32_MAX */
+                             N * T_init * V * n_init must not exceed INT32_MAX */
+  int32_t variables;      /* V, coupled variables per instance (Sec. 3.1); 0: 1 */
+  int32_t equations;      /* Q, governing equations per time point over all V (R+1)
+                             unknowns (Eq. 4, App. A.2's C_t is Q x V(R+1)); 0: V */
+  int32_t row_weights;    /* 0: w holds three scalar weights per instance;
+                             1: w holds one weight per row (layout below) */
 } smnn_plan_desc;
 
 /* Create a plan on the current HIP device: validates the description,

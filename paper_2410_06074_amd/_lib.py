@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "libsmnn.so")
 
 MODES = {"fp64": 0, "fp64r": 1, "fp32r": 2}
 
-STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported order or chunk length",
+STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported order, chunk length or instance shape",
           3: "workspace or factor too small", 4: "HIP runtime error", 5: "wrong current device"}
 
 Q_LEVELS, Q_CHUNK, Q_REFINE, Q_MODE, Q_CHUNK_UPPER, Q_INIT_POINTS, Q_TOP_LEVEL = 1, 2, 3, 4, 5, 6, 7
@@ -41,7 +41,8 @@ class PlanDesc(ctypes.Structure):
                 ("steps", ctypes.POINTER(ctypes.c_int64)), ("steps_uniform", ctypes.c_int64),
                 ("mode", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("chunk_upper", ctypes.c_int32), ("block", ctypes.c_int32), ("max_blocks", ctypes.c_int32),
-                ("init_points", ctypes.c_int32)]
+                ("init_points", ctypes.c_int32), ("variables", ctypes.c_int32), ("equations", ctypes.c_int32),
+                ("row_weights", ctypes.c_int32)]
 
 
 _lib = None

@@ -2,7 +2,8 @@
 
     python -m paper_2410_06074_amd.build
 
-compiles csrc/smnn_kernels.hip once per block size (K = 2..5) in parallel,
+compiles csrc/smnn_kernels.hip once per block size (K = 2..5) and group of
+instance forms in parallel,
 csrc/smnn_misc.hip, csrc/smnn_noalloc.hip and csrc/smnn_api.cpp, and links them into
 paper_2410_06074_amd/libsmnn.so.  Objects go to paper_2410_06074_amd/_build/.
 """
@@ -43,11 +44,14 @@ def _run(cmd):
 def build(jobs: int | None = None, verbose: bool = False) -> str:
     hipcc = _hipcc()
     os.makedirs(BUILD, exist_ok=True)
-    jobs = jobs or max(1, min(6, os.cpu_count() or 1))
+    jobs = jobs or max(1, min(8, os.cpu_count() or 1))
     units = []
-    for K in (2, 3, 4, 5):
-        units.append([hipcc, *COMMON, f"-DSMNN_TU_K={K}", "-c", os.path.join(CSRC, "smnn_kernels.hip"),
-                      "-o", os.path.join(BUILD, f"smnn_kernels_k{K}.o")])
+    # one translation unit per block size K and group of instance forms:
+    # 0 = one variable with scalar weights (and the separator levels),
+    # 1 = one variable with per-row weights, 2 = two coupled variables
+    for K, forms in ((4, 2), (3, 0), (4, 0), (2, 0), (5, 0), (2, 1), (3, 1), (4, 1), (5, 1)):
+        units.append([hipcc, *COMMON, f"-DSMNN_TU_K={K}", f"-DSMNN_TU_FORMS={forms}", "-c",
+                      os.path.join(CSRC, "smnn_kernels.hip"), "-o", os.path.join(BUILD, f"smnn_kernels_k{K}f{forms}.o")])
     units.append([hipcc, *COMMON, "-c", os.path.join(CSRC, "smnn_misc.hip"), "-o", os.path.join(BUILD, "smnn_misc.o")])
     units.append([hipcc, *COMMON, "-c", os.path.join(CSRC, "smnn_noalloc.hip"),
                   "-o", os.path.join(BUILD, "smnn_noalloc.o")])

@@ -15,6 +15,9 @@ using namespace smnn;
 
 struct smnn_plan {
   int R = 0, K = 0, n_init = 0, mode = 0, refine = 0, L0 = 8, L1 = 8;
+  int V = 1, QE = 1;          // variables and governing equations per point (K = V (R+1))
+  bool rows = false;          // per-row weights
+  int form = 0;               // FormId of the level-0 kernels
   int t_init = 1;   // time points carrying initial values
   int top = 0;      // > 0: levels >= top are solved by one launch per solve (launch_top)
   int64_t N = 0, S = 0;
@@ -115,7 +118,7 @@ smnn_status solve_upper(const smnn_plan* p, const Bound& b, int rhs, bool write_
   const Tracer tr{p, st};
   if (nl > 1 && !skip_reduce0)
     SMNN_LAUNCH(tr, SMNN_K_REDUCE0, 0, rhs, 0,
-                launch_reduce0(p->K, p->L0, p->f32, rhs, write_rec, b.lev[0], b.lev[1], a, p->cfg, st));
+                launch_reduce0(p->K, p->L0, p->form, p->f32, rhs, write_rec, b.lev[0], b.lev[1], a, p->cfg, st));
   for (int l = 1; l + 1 < nl && l < lt; ++l)
     SMNN_LAUNCH(tr, SMNN_K_REDUCEN, l, rhs, 0,
                 launch_reduceN(p->K, p->L1, write_rec, l, b.lev[l], b.lev[l + 1], a, p->cfg, st));
@@ -132,8 +135,8 @@ smnn_status backsub0(const smnn_plan* p, const Bound& b, int rhs, int out_mode, 
   const int nl = static_cast<int>(b.lev.size());
   const Tracer tr{p, st};
   SMNN_LAUNCH(tr, SMNN_K_BACKSUB0, 0, rhs, out_mode,
-              launch_backsub0(p->K, p->L0, p->f32, rhs, out_mode, b.lev[0], nl > 1 ? &b.lev[1] : nullptr, a,
-                              p->cfg, st));
+              launch_backsub0(p->K, p->L0, p->form, p->f32, rhs, out_mode, b.lev[0], nl > 1 ? &b.lev[1] : nullptr,
+                              a, p->cfg, st));
   return SMNN_OK;
 }
 
@@ -155,8 +158,26 @@ smnn_status solve_then_reduce(const smnn_plan* p, const Bound& b, int rhs, bool 
   if (s != SMNN_OK) return s;
   const Tracer tr{p, st};
   SMNN_LAUNCH(tr, SMNN_K_BACKSUB_REDUCE0, 0, rhs, 0,
-              launch_backsub_reduce0(p->K, p->L0, p->f32, rhs, b.lev[0], b.lev[1], a, p->cfg, st));
+              launch_backsub_reduce0(p->K, p->L0, p->form, p->f32, rhs, b.lev[0], b.lev[1], a, p->cfg, st));
   return SMNN_OK;
+}
+
+// Per-row weights: the weight buffer (and its gradient) holds the governing
+// weights [S][QE], then the initial weights [N][T_init][V][n_init], then the
+// smoothness weights [S].
+void bind_row_weights(const smnn_plan* p, const void* w, void* dw, Level0Args& a) {
+  if (!p->rows) return;
+  const size_t io = p->f32 ? sizeof(float) : sizeof(double);
+  const size_t ng = static_cast<size_t>(p->S) * p->QE;
+  const size_t ni = static_cast<size_t>(p->N) * p->t_init * p->V * p->n_init;
+  a.wg = w;
+  a.wi = static_cast<const char*>(w) + io * ng;
+  a.ws = static_cast<const char*>(w) + io * (ng + ni);
+  if (dw) {
+    a.dwg = dw;
+    a.dwi = static_cast<char*>(dw) + io * ng;
+    a.dws = static_cast<char*>(dw) + io * (ng + ni);
+  }
 }
 
 smnn_status check_device(const smnn_plan* p) {
@@ -177,18 +198,25 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   if (d->n_init < 0 || d->n_init > d->order + 1) return SMNN_ERR_INVALID_ARG;
   if (d->init_points < 0 || d->init_points > (1 << 30)) return SMNN_ERR_INVALID_ARG;
   if (d->n_inst < 1 || d->n_inst > INT32_MAX) return SMNN_ERR_INVALID_ARG;
+  if (d->variables < 0 || d->equations < 0 || (d->row_weights != 0 && d->row_weights != 1))
+    return SMNN_ERR_INVALID_ARG;
+  const int V = d->variables ? d->variables : 1;
+  const int QE = d->equations ? d->equations : V;
   // the kernels index the initial values with 32-bit offsets
-  if (d->n_inst * d->n_init > INT32_MAX / std::max(1, d->init_points)) return SMNN_ERR_INVALID_ARG;
+  if (d->n_inst * V * d->n_init > INT32_MAX / std::max(1, d->init_points)) return SMNN_ERR_INVALID_ARG;
   if (d->mode < SMNN_MODE_FP64 || d->mode > SMNN_MODE_FP32_REFINED) return SMNN_ERR_INVALID_ARG;
   if (d->refine_steps < -1 || d->refine_steps > 4) return SMNN_ERR_INVALID_ARG;
   if (d->block < 0 || d->block > 256 || d->block % 64 != 0) return SMNN_ERR_INVALID_ARG;
   if (d->max_blocks < 0) return SMNN_ERR_INVALID_ARG;
-  const int K = d->order + 1;
+  if (V > 5 || QE > 5) return SMNN_ERR_UNSUPPORTED;
+  const int K = V * (d->order + 1);
+  const int form = form_id(V, QE, d->row_weights != 0);
+  if (form < 0 || K > 5) return SMNN_ERR_UNSUPPORTED;
   const bool f32 = d->mode == SMNN_MODE_FP32_REFINED;
   const int L0 = d->chunk ? d->chunk : default_chunk(K, false, f32);
   const int L1 = d->chunk_upper ? d->chunk_upper : default_chunk(K, true, f32);
   if (d->chunk < 0 || d->chunk_upper < 0) return SMNN_ERR_INVALID_ARG;
-  if (!supported(K, L0) || !supported(K, L1)) return SMNN_ERR_UNSUPPORTED;
+  if (!supported0(K, L0, form) || !supported(K, L1)) return SMNN_ERR_UNSUPPORTED;
   std::vector<int64_t> T(static_cast<size_t>(d->n_inst));
   for (int64_t i = 0; i < d->n_inst; ++i) {
     T[i] = d->steps ? d->steps[i] : d->steps_uniform;
@@ -199,15 +227,19 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   if (!p) return SMNN_ERR_HIP;
   p->R = d->order;
   p->K = K;
+  p->V = V;
+  p->QE = QE;
+  p->rows = d->row_weights != 0;
+  p->form = form;
   p->n_init = d->n_init;
   p->t_init = d->init_points > 0 ? d->init_points : 1;
   p->mode = d->mode;
   // Default refinement: each step contracts the error by about cond(M) 2^-53.
-  // Block size >= 4 (order >= 3) meets cond(M) ~ 1e13 at h ~ 0.01, where one
-  // step leaves ~1e-8 in FP64 I/O, so the double modes take two there.
+  // Order >= 3 meets cond(M) ~ 1e13 at h ~ 0.01, where one step leaves ~1e-8
+  // in FP64 I/O, so the double modes take two there.
   p->refine = d->mode == SMNN_MODE_FP64 ? 0
               : d->refine_steps >= 0 ? d->refine_steps
-              : (K >= 4 && d->mode == SMNN_MODE_FP64_REFINED) ? 2 : 1;
+              : (d->order >= 3 && d->mode == SMNN_MODE_FP64_REFINED) ? 2 : 1;
   p->L0 = L0;
   p->L1 = L1;
   p->N = d->n_inst;
@@ -227,7 +259,7 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
     const int combos[6][2] = {{RHS_BETA, OUT_STORE}, {RHS_RESID, OUT_STORE}, {RHS_G, OUT_STORE},
                               {RHS_GRESID, OUT_STORE}, {RHS_G, OUT_GRAD}, {RHS_GRESID, OUT_GRAD}};
     for (const auto& cb : combos)
-      if (level0_lds_bytes(K, L0, p->f32, cb[0], cb[1]) > static_cast<size_t>(lds_max)) {
+      if (level0_lds_bytes(K, L0, form, p->f32, cb[0], cb[1]) > static_cast<size_t>(lds_max)) {
         delete p;
         return SMNN_ERR_UNSUPPORTED;
       }
@@ -405,6 +437,7 @@ smnn_status smnn_forward(const smnn_plan* p, const void* c, const void* b, const
   const Bound bd = bind(p, factor, workspace);
   Level0Args a;
   a.c = c; a.d = b; a.s = h; a.u0 = u0; a.w = w;
+  bind_row_weights(p, w, nullptr, a);
   a.n_init = p->n_init;
   a.t_init = p->t_init;
   a.L0 = p->L0;
@@ -449,6 +482,7 @@ smnn_status smnn_backward(const smnn_plan* p, const void* c, const void* b, cons
   Level0Args a;
   a.c = c; a.d = b; a.s = h; a.u0 = u0; a.w = w; a.g = gy; a.y = y;
   a.dc = dc; a.dd = db; a.ds = dh; a.du0 = du0; a.dw = dw; a.dw_part = bd.dwp;
+  bind_row_weights(p, w, dw, a);
   a.n_init = p->n_init;
   a.t_init = p->t_init;
   a.L0 = p->L0;
@@ -480,7 +514,7 @@ smnn_status smnn_backward(const smnn_plan* p, const void* c, const void* b, cons
     }
   }
   const Tracer tr{p, st};
-  SMNN_LAUNCH(tr, SMNN_K_DW, 0, 0, 0, launch_dw_reduce(p->f32, bd.lev[0], a, st));
+  if (!p->rows) SMNN_LAUNCH(tr, SMNN_K_DW, 0, 0, 0, launch_dw_reduce(p->f32, bd.lev[0], a, st));
   SMNN_HIP(launch_info_finalize(a, info, st));
   return SMNN_OK;
 }
@@ -505,10 +539,13 @@ smnn_status time_candidate(const smnn_plan_desc& d, const void* c, const void* b
     if (e1) (void)hipEventDestroy(e1);
     smnn_plan_destroy(p);
   };
+  const size_t QE = static_cast<size_t>(p->QE);
+  const size_t ni = N * p->t_init * p->V * p->n_init;
+  const size_t nw = p->rows ? S * QE + ni + S : N * 3;
   if (hipMalloc(&y, io * S * K) != hipSuccess || hipMalloc(&fac, p->factor_bytes) != hipSuccess ||
-      hipMalloc(&ws, p->workspace_bytes) != hipSuccess || hipMalloc(&dc, io * S * K) != hipSuccess ||
-      hipMalloc(&db, io * S) != hipSuccess || hipMalloc(&dh, io * S) != hipSuccess ||
-      hipMalloc(&du0, io * (N * p->t_init * p->n_init + 1)) != hipSuccess || hipMalloc(&dw, io * N * 3) != hipSuccess ||
+      hipMalloc(&ws, p->workspace_bytes) != hipSuccess || hipMalloc(&dc, io * S * QE * K) != hipSuccess ||
+      hipMalloc(&db, io * S * QE) != hipSuccess || hipMalloc(&dh, io * S) != hipSuccess ||
+      hipMalloc(&du0, io * (ni + 1)) != hipSuccess || hipMalloc(&dw, io * nw) != hipSuccess ||
       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     cleanup();
     return SMNN_ERR_HIP;
@@ -538,7 +575,9 @@ smnn_status smnn_autotune(const smnn_plan_desc* desc, const void* c, const void*
   if (!desc || !c || !b || !h || !w || !gy || !best || iters < 1 || cap < 0) return SMNN_ERR_INVALID_ARG;
   if (desc->n_init > 0 && !u0) return SMNN_ERR_INVALID_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int K = desc->order + 1;
+  const int V = desc->variables > 0 ? desc->variables : 1;
+  const int K = V * (desc->order + 1);
+  const int form = form_id(V, desc->equations > 0 ? desc->equations : V, desc->row_weights != 0);
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -547,7 +586,7 @@ smnn_status smnn_autotune(const smnn_plan_desc* desc, const void* c, const void*
   smnn_tune_result cur{};
   cur.ms = -1.f;
   auto visit = [&](smnn_plan_desc d) -> smnn_status {
-    if (!supported(K, d.chunk) || !supported(K, d.chunk_upper)) return SMNN_OK;
+    if (!supported0(K, d.chunk, form) || !supported(K, d.chunk_upper)) return SMNN_OK;
     float ms = 0.f;
     const smnn_status s = time_candidate(d, c, b, h, u0, w, gy, iters, st, &ms);
     if (s == SMNN_ERR_UNSUPPORTED) return SMNN_OK;

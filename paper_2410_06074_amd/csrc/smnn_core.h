@@ -4,14 +4,17 @@
 // device code (the kernels in smnn_kernels.hip) and from host code (the
 // CPU emulator in tests/emu).  Notation follows the paper
 // (Scalable Mechanistic Neural Networks):
-//   * one instance = one (batch, variable) pair: V = Q = 1, block size
-//     K = R + 1; initial rows (Eq. 5) at the first T_init nodes;
+//   * one instance = V coupled variables (Sec. 3.1) with QE governing
+//     equations per time point, block size K = V (R + 1) (Form below; the
+//     common case is one (batch, variable) pair, V = QE = 1); initial rows
+//     (Eq. 5) at the first T_init nodes;
 //   * node t carries the unknowns y_t (K values);
 //   * M is block tridiagonal (Eq. 10): diagonal blocks A_t ("M_t"),
 //     block (t+1, t) = B_t ("N_t"), right-hand side f_t ("beta_t");
-//   * the blocks come from App. A.2: governing term w_g^2 c_t c_t^T, initial
+//   * the blocks come from App. A.2: governing term w_g^2 C_t^T C_t, initial
 //     term w_i^2 U_t, and the smoothness terms of the rows of Eqs. 6-7
-//     weighted by w_s s_t^r (the weighting before Eq. 9).
+//     weighted by w_s s_t^r (the weighting before Eq. 9), one k x k block
+//     per variable; the weights are scalars or per row (App. A.1's W).
 //
 // Elimination follows the block Cholesky recurrence of Alg. 3 and the
 // substitutions of Alg. 4 (Cholesky form, Eqs. 11-13) inside a chunk of
@@ -252,37 +255,43 @@ SMNN_HD void powers(double s, double (&pw)[Dim<K>::P]) {
   for (int e = 1; e < Dim<K>::P; ++e) pw[e] = pw[e - 1] * s;
 }
 
+// The smoothness rows of Eqs. 6-7 act on one variable's k = R+1 unknowns
+// (App. A.2: S_t = Diag(S_t^*, ..., S_t^*) over the V variables).  The
+// functions below add one variable's k x k block into the K x K block of a
+// node (K = V k), at unknowns off .. off+k-1.
+
 // A += w_s^2 * (smoothness block of the LEFT node of a pair with step s)
-template <int K>
-SMNN_HD void add_left_block(const double (&pw)[Dim<K>::P], double ws2, double (&A)[Dim<K>::Q]) {
-  constexpr Coef<K> C{};
+template <int k, int K = k>
+SMNN_HD void add_left_block(const double (&pw)[Dim<k>::P], double ws2, double (&A)[Dim<K>::Q], int off = 0) {
+  constexpr Coef<k> C{};
 #pragma unroll
-  for (int i = 0; i < K; ++i)
+  for (int i = 0; i < k; ++i)
 #pragma unroll
     for (int j = 0; j <= i; ++j)
-      A[tri(i, j)] += ws2 * pw[i + j] * (C.alpha[i][j] + (i == j ? 1.0 : 0.0));
+      A[tri(off + i, off + j)] += ws2 * pw[i + j] * (C.alpha[i][j] + (i == j ? 1.0 : 0.0));
 }
 
 // A += w_s^2 * (smoothness block of the RIGHT node of a pair with step s)
-template <int K>
-SMNN_HD void add_right_block(const double (&pw)[Dim<K>::P], double ws2, double (&A)[Dim<K>::Q]) {
-  constexpr Coef<K> C{};
+template <int k, int K = k>
+SMNN_HD void add_right_block(const double (&pw)[Dim<k>::P], double ws2, double (&A)[Dim<K>::Q], int off = 0) {
+  constexpr Coef<k> C{};
 #pragma unroll
-  for (int i = 0; i < K; ++i)
+  for (int i = 0; i < k; ++i)
 #pragma unroll
     for (int j = 0; j <= i; ++j)
-      A[tri(i, j)] += ws2 * pw[i + j] *
-                      ((((i + j) & 1) ? -C.alpha[i][j] : C.alpha[i][j]) + (i == j ? 1.0 : 0.0));
+      A[tri(off + i, off + j)] += ws2 * pw[i + j] *
+                                  ((((i + j) & 1) ? -C.alpha[i][j] : C.alpha[i][j]) + (i == j ? 1.0 : 0.0));
 }
 
-// B = w_s^2 * coupling block (row = right node, column = left node)
-template <int K>
-SMNN_HD void coupling_block(const double (&pw)[Dim<K>::P], double ws2, double (&B)[Dim<K>::KK]) {
-  constexpr Coef<K> C{};
+// B = w_s^2 * coupling block (row = right node, column = left node), at
+// rows and columns off .. off+k-1 of the K x K block (the rest untouched)
+template <int k, int K = k>
+SMNN_HD void coupling_block(const double (&pw)[Dim<k>::P], double ws2, double (&B)[Dim<K>::KK], int off = 0) {
+  constexpr Coef<k> C{};
 #pragma unroll
-  for (int i = 0; i < K; ++i)
+  for (int i = 0; i < k; ++i)
 #pragma unroll
-    for (int j = 0; j < K; ++j) B[i * K + j] = ws2 * pw[i + j] * C.nu[i][j];
+    for (int j = 0; j < k; ++j) B[(off + i) * K + off + j] = ws2 * pw[i + j] * C.nu[i][j];
 }
 
 // Row residuals of the 2K weighted smoothness rows of a pair (Eqs. 6-7 scaled
@@ -642,9 +651,26 @@ SMNN_HD int backsub_chunk(const Src& src, int64_t a, int64_t b, bool has_left, b
 }
 
 // ----------------------------------------------------------- level-0 source
-// Per-instance parameters: weights (unsquared), and the shape of the
-// initial rows (Eq. 5): orders < n_init at each of the first t_init points.
-// The initial values themselves are read from memory at those nodes only.
+// Shape of one instance's constraint rows (Sec. 3.1, Eq. 4; App. A.1-A.2):
+// V variables with k = K / V unknowns each (orders 0..R of that variable;
+// block size K = V (R+1)), QE governing equations per time point over all K
+// unknowns (App. A.2's C_t is QE x K), and weights either three scalars per
+// instance (WROW false: w_gov, w_init, w_smooth) or one per row (WROW true:
+// App. A.1's W = diag(w) with a governing weight per (point, equation), an
+// initial weight per (point, variable, order) and a smoothness weight per
+// step, which scales that step's Taylor rows of every variable and order
+// together with s_t^r).
+template <int V_, int QE_, bool WROW_>
+struct Form {
+  static constexpr int V = V_, QE = QE_;
+  static constexpr bool WROW = WROW_;
+};
+using FormScalar = Form<1, 1, false>;
+
+// Per-instance parameters: scalar weights (unsquared; unused with per-row
+// weights), and the shape of the initial rows (Eq. 5): orders < n_init of
+// every variable at each of the first t_init points.  The initial values
+// themselves are read from memory at those nodes only.
 template <int K>
 struct Inst {
   double wg, wi, ws;
@@ -661,15 +687,20 @@ enum RhsMode : int {
 
 // Node data assembled on the fly from the per-step inputs of one instance.
 // TIO is the element type of the arrays in memory (double or float).
-template <int K, class TIO, int RHS>
+template <int K, class TIO, int RHS, class F = FormScalar>
 struct Src0 {
-  const TIO* c;      // [..][K] node i of this instance is row o + i
-  const TIO* d;      // [..]
+  static constexpr int V = F::V, QE = F::QE, k = K / F::V;
+  static_assert(k * V == K, "block size is V (R+1)");
+  const TIO* c;      // [..][QE][K] node i of this instance is row o + i
+  const TIO* d;      // [..][QE]
   const TIO* s;      // [..]  (s of the last node unused)
   const TIO* g;      // [..][K]  dl/dy (RHS_G, RHS_GRESID)
   const TIO* v;      // [..][K]  previous iterate (RHS_RESID, RHS_GRESID)
-  const TIO* u = nullptr;   // initial values of every instance, [N][t_init][n_init]
-  int uo = 0;               // element offset of this instance's block in u
+  const TIO* wg = nullptr;   // [..][QE] governing weights (per-row weights)
+  const TIO* wsm = nullptr;  // [..]     smoothness weight of the pair (i, i+1) (per-row weights)
+  const TIO* u = nullptr;    // initial values of every instance, [N][t_init][V][n_init]
+  const TIO* wi = nullptr;   // initial weights, same layout as u (per-row weights)
+  int uo = 0;                // element offset of this instance's block in u (and wi)
   int64_t n;
   int64_t o = 0;     // row of node 0 in the arrays above
   Inst<K> p;
@@ -679,39 +710,78 @@ struct Src0 {
   mutable int64_t carry_node = -1;
 
   SMNN_HD double ld(const TIO* ptr, int64_t i) const { return static_cast<double>(ptr[o + i]); }
-  // initial value of order r at node i < t_init
-  SMNN_HD double uval(int64_t i, int r) const {
-    return static_cast<double>(u[uo + static_cast<int>(i) * p.n_init + r]);
-  }
   SMNN_HD double ldk(const TIO* ptr, int64_t i, int r) const { return static_cast<double>(ptr[(o + i) * K + r]); }
+  // coefficient j of governing equation q at node i; its right-hand side
+  SMNN_HD double ldc(int64_t i, int q, int j) const { return static_cast<double>(c[((o + i) * QE + q) * K + j]); }
+  SMNN_HD double ldd(int64_t i, int q) const { return static_cast<double>(d[(o + i) * QE + q]); }
+  // weights (unsquared) of governing row (i, q), of the pair (i, i+1) and of
+  // initial row (i, variable vv, order r)
+  SMNN_HD double gov_w(int64_t i, int q) const {
+    if constexpr (F::WROW) return static_cast<double>(wg[(o + i) * QE + q]);
+    else return p.wg;
+  }
+  SMNN_HD double smooth_w(int64_t i) const {
+    if constexpr (F::WROW) return ld(wsm, i);
+    else return p.ws;
+  }
+  SMNN_HD int uidx(int64_t i, int vv, int r) const {
+    return uo + (static_cast<int>(i) * V + vv) * p.n_init + r;
+  }
+  SMNN_HD double init_w(int64_t i, int vv, int r) const {
+    if constexpr (F::WROW) return static_cast<double>(wi[uidx(i, vv, r)]);
+    else return p.wi;
+  }
+  // initial value of order r of variable vv at node i < t_init
+  SMNN_HD double uval(int64_t i, int vv, int r) const { return static_cast<double>(u[uidx(i, vv, r)]); }
 
   SMNN_HD void coupling(int64_t i, double (&B)[Dim<K>::KK]) const {
-    double pw[Dim<K>::P];
-    powers<K>(ld(s, i), pw);
-    coupling_block<K>(pw, p.ws * p.ws, B);
+    double pw[Dim<k>::P];
+    powers<k>(ld(s, i), pw);
+    const double w = smooth_w(i);
+    if (V > 1) {
+#pragma unroll
+      for (int e = 0; e < Dim<K>::KK; ++e) B[e] = 0.0;
+    }
+#pragma unroll
+    for (int vv = 0; vv < V; ++vv) coupling_block<k, K>(pw, w * w, B, vv * k);
   }
 
   // f = A^T W (b - A v) (RHS_RESID) or g - A^T W A v (RHS_GRESID) at node i,
-  // evaluated row by row from the constraint rows touching the node.
+  // evaluated row by row from the constraint rows touching the node.  ci is
+  // governing row 0 of the node (the caller has it loaded).
   SMNN_HD void residual_rhs(int64_t i, const double (&ci)[K], bool has_next, bool has_prev,
-                            const double (&pl)[Dim<K>::P], const double (&pr)[Dim<K>::P], double (&f)[K]) const {
+                            const double (&pl)[Dim<k>::P], const double (&pr)[Dim<k>::P], double (&f)[K]) const {
 #if defined(__clang__)
 #pragma clang fp contract(off)
 #endif
-    const double wg2 = p.wg * p.wg, wi2 = p.wi * p.wi;
     double vi[K];
 #pragma unroll
     for (int r = 0; r < K; ++r) vi[r] = ldk(v, i, r);
-    double e = (RHS == RHS_RESID) ? ld(d, i) : 0.0;
 #pragma unroll
-    for (int r = 0; r < K; ++r) e = fma(-ci[r], vi[r], e);
-    const double we = wg2 * e;
+    for (int q = 0; q < QE; ++q) {
+      double cq[K];
 #pragma unroll
-    for (int r = 0; r < K; ++r) f[r] = (RHS == RHS_GRESID) ? fma(ci[r], we, ldk(g, i, r)) : ci[r] * we;
+      for (int r = 0; r < K; ++r) cq[r] = q == 0 ? ci[r] : ldc(i, q, r);
+      const double w = gov_w(i, q);
+      double e = (RHS == RHS_RESID) ? ldd(i, q) : 0.0;
+#pragma unroll
+      for (int r = 0; r < K; ++r) e = fma(-cq[r], vi[r], e);
+      const double we = (w * w) * e;
+#pragma unroll
+      for (int r = 0; r < K; ++r) {
+        if (q == 0) f[r] = (RHS == RHS_GRESID) ? fma(cq[r], we, ldk(g, i, r)) : cq[r] * we;
+        else f[r] = fma(cq[r], we, f[r]);
+      }
+    }
     if (i < p.t_init) {
 #pragma unroll
-      for (int r = 0; r < K; ++r)
-        if (r < p.n_init) f[r] += wi2 * ((RHS == RHS_RESID ? uval(i, r) : 0.0) - vi[r]);
+      for (int vv = 0; vv < V; ++vv)
+#pragma unroll
+        for (int r = 0; r < k; ++r)
+          if (r < p.n_init) {
+            const double w = init_w(i, vv, r);
+            f[vv * k + r] += (w * w) * ((RHS == RHS_RESID ? uval(i, vv, r) : 0.0) - vi[vv * k + r]);
+          }
     }
     if (has_prev) {
       double cr[K];
@@ -719,106 +789,162 @@ struct Src0 {
 #pragma unroll
         for (int r = 0; r < K; ++r) cr[r] = carry[r];
       } else {
-        double vp[K], cl[K];
+        const double w = smooth_w(i - 1);
 #pragma unroll
-        for (int r = 0; r < K; ++r) vp[r] = ldk(v, i - 1, r);
-        pair_residual<K>(pl, p.ws, vp, vi, cl, cr);
+        for (int vv = 0; vv < V; ++vv) {
+          double vp[k], vc[k], cl[k], crv[k];
+#pragma unroll
+          for (int r = 0; r < k; ++r) { vp[r] = ldk(v, i - 1, vv * k + r); vc[r] = vi[vv * k + r]; }
+          pair_residual<k>(pl, w, vp, vc, cl, crv);
+#pragma unroll
+          for (int r = 0; r < k; ++r) cr[vv * k + r] = crv[r];
+        }
       }
 #pragma unroll
       for (int r = 0; r < K; ++r) f[r] += cr[r];
     }
     if (has_next) {
-      double vn[K], cl[K];
+      const double w = smooth_w(i);
 #pragma unroll
-      for (int r = 0; r < K; ++r) vn[r] = ldk(v, i + 1, r);
-      pair_residual<K>(pr, p.ws, vi, vn, cl, carry);
+      for (int vv = 0; vv < V; ++vv) {
+        double vc[k], vn[k], cl[k], crv[k];
+#pragma unroll
+        for (int r = 0; r < k; ++r) { vc[r] = vi[vv * k + r]; vn[r] = ldk(v, i + 1, vv * k + r); }
+        pair_residual<k>(pr, w, vc, vn, cl, crv);
+#pragma unroll
+        for (int r = 0; r < k; ++r) {
+          carry[vv * k + r] = crv[r];
+          f[vv * k + r] += cl[r];
+        }
+      }
       carry_node = i + 1;
-#pragma unroll
-      for (int r = 0; r < K; ++r) f[r] += cl[r];
     }
   }
 
   SMNN_HD void load(int64_t i, double (&A)[Dim<K>::Q], double (&f)[K], double (&Bp)[Dim<K>::KK]) const {
     double ci[K];
 #pragma unroll
-    for (int r = 0; r < K; ++r) ci[r] = ldk(c, i, r);
-    const double wg2 = p.wg * p.wg, wi2 = p.wi * p.wi, ws2 = p.ws * p.ws;
+    for (int r = 0; r < K; ++r) ci[r] = ldc(i, 0, r);
+    // governing rows: w_q^2 c_q c_q^T (App. A.2's C_t^T C_t, weighted per row)
 #pragma unroll
-    for (int r = 0; r < K; ++r)
+    for (int q = 0; q < QE; ++q) {
+      double cq[K];
 #pragma unroll
-      for (int q = 0; q <= r; ++q) A[tri(r, q)] = wg2 * ci[r] * ci[q];
-    if (i < p.t_init) {
+      for (int r = 0; r < K; ++r) cq[r] = q == 0 ? ci[r] : ldc(i, q, r);
+      const double w = gov_w(i, q), wg2 = w * w;
 #pragma unroll
       for (int r = 0; r < K; ++r)
-        if (r < p.n_init) A[tri(r, r)] += wi2;
+#pragma unroll
+        for (int j = 0; j <= r; ++j) {
+          if (q == 0) A[tri(r, j)] = wg2 * cq[r] * cq[j];
+          else A[tri(r, j)] += wg2 * cq[r] * cq[j];
+        }
+      if (RHS == RHS_BETA) {
+        const double dq = ldd(i, q);
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+          if (q == 0) f[r] = wg2 * cq[r] * dq;
+          else f[r] += wg2 * cq[r] * dq;
+        }
+      }
     }
-    double pl[Dim<K>::P], pr[Dim<K>::P];
+    if (i < p.t_init) {
+#pragma unroll
+      for (int vv = 0; vv < V; ++vv)
+#pragma unroll
+        for (int r = 0; r < k; ++r)
+          if (r < p.n_init) {
+            const double w = init_w(i, vv, r), wi2 = w * w;
+            A[tri(vv * k + r, vv * k + r)] += wi2;
+            if (RHS == RHS_BETA) f[vv * k + r] += wi2 * uval(i, vv, r);
+          }
+    }
+    double pl[Dim<k>::P], pr[Dim<k>::P];
     const bool has_next = i + 1 < n, has_prev = i > 0;
     if (has_next) {
-      powers<K>(ld(s, i), pr);
-      add_left_block<K>(pr, ws2, A);
+      powers<k>(ld(s, i), pr);
+      const double w = smooth_w(i);
+#pragma unroll
+      for (int vv = 0; vv < V; ++vv) add_left_block<k, K>(pr, w * w, A, vv * k);
     }
     if (has_prev) {
-      powers<K>(ld(s, i - 1), pl);
-      add_right_block<K>(pl, ws2, A);
-      coupling_block<K>(pl, ws2, Bp);
-    }
-    if (RHS == RHS_BETA) {
-      const double di = ld(d, i);
+      powers<k>(ld(s, i - 1), pl);
+      const double w = smooth_w(i - 1);
+      if (V > 1) {
 #pragma unroll
-      for (int r = 0; r < K; ++r) f[r] = wg2 * ci[r] * di;
-      if (i < p.t_init) {
-#pragma unroll
-        for (int r = 0; r < K; ++r)
-          if (r < p.n_init) f[r] += wi2 * uval(i, r);
+        for (int e = 0; e < Dim<K>::KK; ++e) Bp[e] = 0.0;
       }
-    } else if (RHS == RHS_G) {
+#pragma unroll
+      for (int vv = 0; vv < V; ++vv) {
+        add_right_block<k, K>(pl, w * w, A, vv * k);
+        coupling_block<k, K>(pl, w * w, Bp, vv * k);
+      }
+    }
+    if (RHS == RHS_G) {
 #pragma unroll
       for (int r = 0; r < K; ++r) f[r] = ldk(g, i, r);
-    } else {
+    } else if (RHS != RHS_BETA) {
       residual_rhs(i, ci, has_next, has_prev, pl, pr, f);
     }
   }
 };
 
-// Level-0 solution sink: out_i = (v_i +) x_i in the I/O type.
-template <class TIO, bool ADD>
+// Level-0 solution sink: out_i = (v_i +) x_i in the I/O type.  Rows of out
+// are RS elements apart (0: K, dense).
+template <class TIO, bool ADD, int RS = 0>
 struct StoreSink {
-  TIO* out;        // [..][K]: node i is row oo + i
+  TIO* out;        // [..][RS]: node i is row oo + i, its first K elements
   const TIO* v;    // previous iterate (ADD): node i is row vo + i
   int64_t vo = 0;
   int64_t oo = 0;
   template <int K>
   SMNN_HD void node(int64_t i, const double (&x)[K]) {
+    constexpr int W = RS ? RS : K;
 #pragma unroll
     for (int e = 0; e < K; ++e) {
       double val = x[e];
       if (ADD) val += static_cast<double>(v[(vo + i) * K + e]);
-      out[(oo + i) * K + e] = static_cast<TIO>(val);
+      out[(oo + i) * W + e] = static_cast<TIO>(val);
     }
   }
 };
 
 // Level-0 gradient sink.  As the back-substitution finishes node i (in
 // decreasing order) with lam_i = (v_i +) x_i it forms the gradients of the
-// rows the chunk owns: the governing row of node i, the initial rows when
-// i = 0, and the smoothness pair (i, i+1), using the node finished just
+// rows the chunk owns: the governing rows of node i, the initial rows when
+// i < t_init, and the smoothness pair (i, i+1), using the node finished just
 // before.  Per weighted row a~.y = b~ with rho = a~.y - b~ and mu = a~.lam,
 // dl/dtheta = -[(da~.lam) rho + mu (da~.y - db~)] (Eq. 14 chained through the
-// row).  dw accumulates this chunk's partial sums.
-template <int K, class TIO, bool ADD>
+// row); for the row's own weight sigma, dl/dsigma = -2 rho mu / sigma.  With
+// scalar weights dw accumulates this chunk's partial sums of the three
+// weight gradients; with per-row weights every row's is written (dwg, dws
+// like dd, ds; dwi like du0).
+template <int K, class TIO, bool ADD, class F = FormScalar>
 struct GradSink {
+  static constexpr int V = F::V, QE = F::QE, k = K / F::V;
   const TIO *c, *d, *s, *y, *v;   // inputs: node i is row o + i
+  const TIO *wg = nullptr, *wsm = nullptr;   // per-row weights, rows as d and s
   TIO *dc, *dd, *ds;              // outputs: node i is row oo + i
-  TIO* du0;                       // this instance's [t_init][n_init]
-  const TIO* u = nullptr;         // initial values of every instance, [N][t_init][n_init]
-  int uo = 0;                     // element offset of this instance's block in u
+  TIO *dwg = nullptr, *dws = nullptr;        // per-row weight gradients, rows as dd and ds
+  TIO* du0;                       // this instance's [t_init][V][n_init]
+  TIO* dwi = nullptr;             // this instance's initial-weight gradients, as du0
+  const TIO* u = nullptr;         // initial values of every instance, [N][t_init][V][n_init]
+  const TIO* wi = nullptr;        // initial weights, as u (per-row weights)
+  int uo = 0;                     // element offset of this instance's block in u (and wi)
   int64_t o = 0, oo = 0;
   Inst<K> p;
   double lam_n[K], y_n[K];   // node i+1 (the one finished before)
   bool have_next = false;
   double dw[3] = {0.0, 0.0, 0.0};
 
+  SMNN_HD double gov_w(int64_t i, int q) const {
+    if constexpr (F::WROW) return static_cast<double>(wg[(o + i) * QE + q]);
+    else return p.wg;
+  }
+  SMNN_HD double smooth_w(int64_t i) const {
+    if constexpr (F::WROW) return static_cast<double>(wsm[o + i]);
+    else return p.ws;
+  }
   SMNN_HD void lam_y(int64_t i, const double (&x)[K], double (&lam)[K], double (&yi)[K]) const {
 #pragma unroll
     for (int e = 0; e < K; ++e) {
@@ -827,33 +953,57 @@ struct GradSink {
     }
   }
   SMNN_HD void governing(int64_t i, const double (&lam)[K], const double (&yi)[K]) {
-    const double wg2 = p.wg * p.wg;
-    double e = -static_cast<double>(d[o + i]), f = 0.0;
 #pragma unroll
-    for (int r = 0; r < K; ++r) {
-      const double cr = static_cast<double>(c[(o + i) * K + r]);
-      e = fma(cr, yi[r], e);
-      f = fma(cr, lam[r], f);
-    }
+    for (int q = 0; q < QE; ++q) {
+      const double w = gov_w(i, q), wg2 = w * w;
+      double e = -static_cast<double>(d[(o + i) * QE + q]), f = 0.0;
 #pragma unroll
-    for (int r = 0; r < K; ++r) dc[(oo + i) * K + r] = static_cast<TIO>(-wg2 * (e * lam[r] + f * yi[r]));
-    dd[oo + i] = static_cast<TIO>(wg2 * f);
-    dw[0] += -2.0 * p.wg * e * f;
-    if (i < p.t_init) {
+      for (int r = 0; r < K; ++r) {
+        const double cr = static_cast<double>(c[((o + i) * QE + q) * K + r]);
+        e = fma(cr, yi[r], e);
+        f = fma(cr, lam[r], f);
+      }
 #pragma unroll
       for (int r = 0; r < K; ++r)
-        if (r < p.n_init) {
-          const double ur = static_cast<double>(u[uo + static_cast<int>(i) * p.n_init + r]);
-          du0[i * p.n_init + r] = static_cast<TIO>(p.wi * p.wi * lam[r]);
-          dw[1] += -2.0 * p.wi * (yi[r] - ur) * lam[r];
-        }
+        dc[((oo + i) * QE + q) * K + r] = static_cast<TIO>(-wg2 * (e * lam[r] + f * yi[r]));
+      dd[(oo + i) * QE + q] = static_cast<TIO>(wg2 * f);
+      if constexpr (F::WROW) dwg[(oo + i) * QE + q] = static_cast<TIO>(-2.0 * w * e * f);
+      else dw[0] += -2.0 * p.wg * e * f;
+    }
+    if (i < p.t_init) {
+#pragma unroll
+      for (int vv = 0; vv < V; ++vv)
+#pragma unroll
+        for (int r = 0; r < k; ++r)
+          if (r < p.n_init) {
+            const int ui = (static_cast<int>(i) * V + vv) * p.n_init + r;
+            const double ur = static_cast<double>(u[uo + ui]);
+            const double w = F::WROW ? static_cast<double>(wi[uo + ui]) : p.wi;
+            const double l = lam[vv * k + r];
+            du0[ui] = static_cast<TIO>(w * w * l);
+            if constexpr (F::WROW) dwi[ui] = static_cast<TIO>(-2.0 * w * (yi[vv * k + r] - ur) * l);
+            else dw[1] += -2.0 * p.wi * (yi[vv * k + r] - ur) * l;
+          }
     }
   }
   SMNN_HD void pair(int64_t i, const double (&lam)[K], const double (&yi)[K]) {
+    const double si = static_cast<double>(s[o + i]), w = smooth_w(i);
     double g_s = 0.0, g_w = 0.0;
-    pair_grad<K>(static_cast<double>(s[o + i]), p.ws, yi, y_n, lam, lam_n, g_s, g_w);
+#pragma unroll
+    for (int vv = 0; vv < V; ++vv) {
+      double yt[k], yn[k], lt[k], ln[k], gs, gw;
+#pragma unroll
+      for (int r = 0; r < k; ++r) {
+        yt[r] = yi[vv * k + r]; yn[r] = y_n[vv * k + r];
+        lt[r] = lam[vv * k + r]; ln[r] = lam_n[vv * k + r];
+      }
+      pair_grad<k>(si, w, yt, yn, lt, ln, gs, gw);
+      g_s += gs;
+      g_w += gw;
+    }
     ds[oo + i] = static_cast<TIO>(g_s);
-    dw[2] += g_w;
+    if constexpr (F::WROW) dws[oo + i] = static_cast<TIO>(g_w);
+    else dw[2] += g_w;
   }
   // the chunk's right separator (owned; finished by the level above)
   SMNN_HD void start(int64_t i, const double (&x)[K]) {
@@ -874,11 +1024,19 @@ struct GradSink {
     for (int e = 0; e < K; ++e) { lam_n[e] = lam[e]; y_n[e] = yi[e]; }
     have_next = true;
   }
+  // the instance's last point: its step slot enters no row
+  SMNN_HD void last_point(int64_t n) {
+    ds[oo + n - 1] = static_cast<TIO>(0.0);
+    if constexpr (F::WROW) dws[oo + n - 1] = static_cast<TIO>(0.0);
+  }
   // initial points past the instance's last node (n < t_init) have no row:
   // their gradient is zero (called by the lane owning the instance's end)
   SMNN_HD void zero_past_end(int64_t n) {
     for (int64_t t = n; t < p.t_init; ++t)
-      for (int r = 0; r < p.n_init; ++r) du0[t * p.n_init + r] = static_cast<TIO>(0.0);
+      for (int e = 0; e < V * p.n_init; ++e) {
+        du0[t * V * p.n_init + e] = static_cast<TIO>(0.0);
+        if constexpr (F::WROW) dwi[t * V * p.n_init + e] = static_cast<TIO>(0.0);
+      }
   }
   // the chunk's left separator: only the smoothness pair (i, i+1) is owned here
   SMNN_HD void left(int64_t i, const double (&x)[K]) {

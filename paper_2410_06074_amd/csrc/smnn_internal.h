@@ -22,22 +22,28 @@ struct LevelDev {
 // Level-0 (per time step) arrays of one call.  Element type is double or
 // float (fp32 I/O form) for every pointer typed void.
 struct Level0Args {
-  const void* c = nullptr;   // [S][K]
-  const void* d = nullptr;   // [S]
+  const void* c = nullptr;   // [S][QE][K]
+  const void* d = nullptr;   // [S][QE]
   const void* s = nullptr;   // [S]
-  const void* u0 = nullptr;  // [N][t_init][n_init]
+  const void* u0 = nullptr;  // [N][t_init][V][n_init]
   const void* w = nullptr;   // [N][3]
   const void* g = nullptr;   // [S][K]  dl/dy
   const void* v = nullptr;   // [S][K]  previous iterate (refinement passes)
   void* out = nullptr;       // [S][K]  result (x, or v + x)
   const void* y = nullptr;   // [S][K]  forward solution (gradient pass)
-  void* dc = nullptr;        // [S][K]
-  void* dd = nullptr;        // [S]
+  void* dc = nullptr;        // [S][QE][K]
+  void* dd = nullptr;        // [S][QE]
   void* ds = nullptr;        // [S]
-  void* du0 = nullptr;       // [N][t_init][n_init]
+  void* du0 = nullptr;       // [N][t_init][V][n_init]
   double* dw_part = nullptr; // [chunks0][3] per-chunk partial sums
   void* dw = nullptr;        // [N][3]
   uint32_t* info = nullptr;  // [N] smallest failing step + 1 (UINT32_MAX = none)
+  const void* wg = nullptr;  // per-row weights: [S][QE] governing,
+  const void* wi = nullptr;  //   [N][t_init][V][n_init] initial,
+  const void* ws = nullptr;  //   [S] smoothness (of the rows between points t and t+1)
+  void* dwg = nullptr;       // their gradients, same layouts
+  void* dwi = nullptr;
+  void* dws = nullptr;
   int n_init = 0;
   int t_init = 1;            // points carrying initial values
   int L0 = 8, L1 = 8;        // chunk lengths of level 0 and of levels >= 1
@@ -54,22 +60,39 @@ struct Launch {
 
 enum OutMode : int { OUT_STORE = 0, OUT_GRAD = 1 };
 
-// All return hipSuccess or the launch error.  K = R+1, L = chunk length,
-// f32 selects the float I/O form.
-hipError_t launch_reduce0(int K, int L, bool f32, int rhs_mode, bool write_rec, const LevelDev& l0,
+// Instance forms of the level-0 kernels (smnn_core.h Form): variables V,
+// governing equations QE per point, per-row weights.
+enum FormId : int {
+  SMNN_FORM_SCALAR = 0,     // V = QE = 1, three scalar weights per instance
+  SMNN_FORM_ROWS = 1,       // V = QE = 1, per-row weights
+  SMNN_FORM_V2 = 2,         // V = QE = 2, scalar weights
+  SMNN_FORM_V2_ROWS = 3,    // V = QE = 2, per-row weights
+  SMNN_FORM_V2_Q1 = 4       // V = 2, QE = 1, scalar weights
+};
+// Form id of (V, QE, per-row weights), -1 if none is built.
+inline int form_id(int V, int QE, bool rows) {
+  if (V == 1 && QE == 1) return rows ? SMNN_FORM_ROWS : SMNN_FORM_SCALAR;
+  if (V == 2 && QE == 2) return rows ? SMNN_FORM_V2_ROWS : SMNN_FORM_V2;
+  if (V == 2 && QE == 1 && !rows) return SMNN_FORM_V2_Q1;
+  return -1;
+}
+
+// All return hipSuccess or the launch error.  K = V (R+1), L = chunk length,
+// form = FormId of the level-0 kernels, f32 selects the float I/O form.
+hipError_t launch_reduce0(int K, int L, int form, bool f32, int rhs_mode, bool write_rec, const LevelDev& l0,
                           const LevelDev& l1, const Level0Args& a, const Launch& cfg, hipStream_t st);
 hipError_t launch_reduceN(int K, int L, bool write_rec, int level, const LevelDev& l, const LevelDev& lnext,
                           const Level0Args& a, const Launch& cfg, hipStream_t st);
 hipError_t launch_backsubN(int K, int L, int level, const LevelDev& l, const LevelDev* lnext,
                            const Level0Args& a, const Launch& cfg, hipStream_t st);
-hipError_t launch_backsub0(int K, int L, bool f32, int rhs_mode, int out_mode, const LevelDev& l0,
+hipError_t launch_backsub0(int K, int L, int form, bool f32, int rhs_mode, int out_mode, const LevelDev& l0,
                            const LevelDev* l1, const Level0Args& a, const Launch& cfg, hipStream_t st);
 // Level-0 back-substitution of a solve with right-hand side rhs_in (beta or
 // dl/dy), storing the iterate to a.out, fused with the level-0 reduce of the
 // refinement solve that follows (residual or adjoint residual of that
 // iterate; writes the level-1 right-hand sides only).
-hipError_t launch_backsub_reduce0(int K, int L, bool f32, int rhs_in, const LevelDev& l0, const LevelDev& l1,
-                                  const Level0Args& a, const Launch& cfg, hipStream_t st);
+hipError_t launch_backsub_reduce0(int K, int L, int form, bool f32, int rhs_in, const LevelDev& l0,
+                                  const LevelDev& l1, const Level0Args& a, const Launch& cfg, hipStream_t st);
 // Levels >= level of a solve in one launch, one wave per instance (every
 // instance must have at most 64 chunks at that level); writes that level's x.
 hipError_t launch_top(int K, int L, int level, const LevelDev& l, const Level0Args& a, const Launch& cfg,
@@ -80,14 +103,25 @@ hipError_t launch_info_init(const Level0Args& a, hipStream_t st);
 
 // LDS bytes one wave of a level-0 kernel stages its tile in (0 if (K, L) is
 // not compiled in).  The largest variant of a mode is the gradient pass.
-size_t level0_lds_bytes(int K, int L, bool f32, int rhs_mode, int out_mode);
+size_t level0_lds_bytes(int K, int L, int form, bool f32, int rhs_mode, int out_mode);
 hipError_t launch_info_finalize(const Level0Args& a, int32_t* info, hipStream_t st);
 
-bool supported(int K, int L);
+bool supported(int K, int L);            // separator levels (and the scalar form at level 0)
+bool supported0(int K, int L, int form);  // level-0 kernels of the form
 
-// Name of a per-block-size launcher (smnn_kernels.hip is built once per K).
+// Name of a per-block-size launcher (smnn_kernels.hip is built once per K
+// and group of instance forms).
+#ifndef SMNN_TU_FORMS
+#define SMNN_TU_FORMS 0
+#endif
+#if SMNN_TU_FORMS == 0
 #define SMNN_KFN_CAT2(a, b) a##_k##b
 #define SMNN_KFN_CAT(a, b) SMNN_KFN_CAT2(a, b)
 #define SMNN_KFN(name) SMNN_KFN_CAT(name, SMNN_TU_K)
+#else
+#define SMNN_KFN_CAT2(a, b, g) a##_k##b##f##g
+#define SMNN_KFN_CAT(a, b, g) SMNN_KFN_CAT2(a, b, g)
+#define SMNN_KFN(name) SMNN_KFN_CAT(name, SMNN_TU_K, SMNN_TU_FORMS)
+#endif
 
 }  // namespace smnn

@@ -39,9 +39,11 @@
 #include "smnn_core.h"
 #include "smnn_internal.h"
 
-// This file is compiled once per block size K (-DSMNN_TU_K=2..5); each
+// This file is compiled once per block size K (-DSMNN_TU_K=2..5) and group
+// of instance forms (-DSMNN_TU_FORMS=0..2, see the lists at the end); each
 // translation unit instantiates the chunk lengths listed for its K and
-// exports launchers suffixed _k<K> (see smnn_internal.h).
+// exports launchers suffixed _k<K> (forms group 0) or _k<K>f<group> (see
+// smnn_internal.h).
 #ifndef SMNN_TU_K
 #error "compile with -DSMNN_TU_K=<block size>"
 #endif
@@ -74,7 +76,8 @@ __device__ __forceinline__ int64_t wave_count(const Level0Args& a) { return a.nw
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 
 // ---------------------------------------------------------- LDS staging
-// Per-step arrays a level-0 kernel variant reads (c and s always).
+// Per-step arrays a level-0 kernel variant reads (c and s always; the
+// per-row governing and smoothness weights with per-row weights).
 template <int RHS, int OUT>
 struct Reads {
   static constexpr bool d = RHS == RHS_BETA || RHS == RHS_RESID || OUT == OUT_GRAD;
@@ -85,20 +88,24 @@ struct Reads {
 
 // Byte layout of one wave's LDS slice: ROWS steps of each array read, every
 // array 16-byte aligned.  A tile spans at most 64 chunks of L steps plus the
-// step before and the step after.
-template <int K, int L, class TIO, int RHS, int OUT>
+// step before and the step after.  Rows of c hold QE K values, rows of b and
+// of the governing weights QE.
+template <int K, int L, class TIO, int RHS, int OUT, class F = FormScalar>
 struct Stage {
   using RD = Reads<RHS, OUT>;
   static constexpr int ROWS = WAVE * L + 2;
   static constexpr size_t al(size_t b) { return (b + 15) / 16 * 16; }
   static constexpr size_t ROW_K = al(sizeof(TIO) * K * ROWS), ROW_1 = al(sizeof(TIO) * ROWS);
+  static constexpr size_t ROW_C = al(sizeof(TIO) * F::QE * K * ROWS), ROW_D = al(sizeof(TIO) * F::QE * ROWS);
   static constexpr size_t C = 0;
-  static constexpr size_t S = C + ROW_K;
+  static constexpr size_t S = C + ROW_C;
   static constexpr size_t D = S + ROW_1;
-  static constexpr size_t G = D + (RD::d ? ROW_1 : 0);
+  static constexpr size_t G = D + (RD::d ? ROW_D : 0);
   static constexpr size_t V = G + (RD::g ? ROW_K : 0);
   static constexpr size_t Y = G;   // dl/dy is read by the forward sweep only
-  static constexpr size_t BYTES = V + (RD::v ? ROW_K : 0);
+  static constexpr size_t WG = V + (RD::v ? ROW_K : 0);
+  static constexpr size_t WS = WG + (F::WROW ? ROW_D : 0);
+  static constexpr size_t BYTES = WS + (F::WROW ? ROW_1 : 0);
 };
 
 // Wave-cooperative copy of rows [lo, hi) of an array with w elements per row
@@ -115,17 +122,30 @@ __device__ __forceinline__ void stage_rows(const void* src, int w, int64_t lo, i
     if (b + lane < ndw) __builtin_amdgcn_global_load_lds(gsrc + b + lane, l + b, 4, 0, 0);
 }
 
+// Per-row weights: the governing weights (QE per row) and the smoothness
+// weight of each step.
+template <int K, int L, class TIO, int RHS, int OUT, class F>
+__device__ __forceinline__ void stage_weights(const Level0Args& a, int64_t lo, int64_t hi, unsigned char* sl,
+                                              int lane) {
+  using ST = Stage<K, L, TIO, RHS, OUT, F>;
+  if constexpr (F::WROW) {
+    stage_rows<TIO>(a.wg, F::QE, lo, hi, sl + ST::WG, lane);
+    stage_rows<TIO>(a.ws, 1, lo, hi, sl + ST::WS, lane);
+  }
+}
+
 // Copies rows [lo, hi) of every array the variant reads into the slice.
-template <int K, int L, class TIO, int RHS, int OUT>
+template <int K, int L, class TIO, int RHS, int OUT, class F>
 __device__ __forceinline__ void stage_tile(const Level0Args& a, int64_t lo, int64_t hi, unsigned char* sl,
                                            int lane) {
-  using ST = Stage<K, L, TIO, RHS, OUT>;
+  using ST = Stage<K, L, TIO, RHS, OUT, F>;
   using RD = Reads<RHS, OUT>;
-  stage_rows<TIO>(a.c, K, lo, hi, sl + ST::C, lane);
+  stage_rows<TIO>(a.c, F::QE * K, lo, hi, sl + ST::C, lane);
   stage_rows<TIO>(a.s, 1, lo, hi, sl + ST::S, lane);
-  if (RD::d) stage_rows<TIO>(a.d, 1, lo, hi, sl + ST::D, lane);
+  if (RD::d) stage_rows<TIO>(a.d, F::QE, lo, hi, sl + ST::D, lane);
   if (RD::g) stage_rows<TIO>(a.g, K, lo, hi, sl + ST::G, lane);
   if (RD::v) stage_rows<TIO>(a.v, K, lo, hi, sl + ST::V, lane);
+  stage_weights<K, L, TIO, RHS, OUT, F>(a, lo, hi, sl, lane);
 }
 
 // Rows of the tile of chunks [g0, g1): from the step before the first chunk
@@ -140,15 +160,21 @@ __device__ __forceinline__ void tile_rows(const LevelDev& l0, int64_t g0, int64_
 }
 
 // Wave-cooperative copy of rows [r0, r1) (w elements each) from a slot of the
-// wave's LDS slice (slice row = global row - lo) to global memory: every
-// store instruction writes 64 consecutive elements.
-template <class T>
+// wave's LDS slice (slice row = global row - lo; rows LS elements apart in
+// the slot, 0: w) to global memory: every store instruction writes 64
+// consecutive elements.
+template <class T, int LS = 0>
 __device__ __forceinline__ void unstage_rows(void* dst, int w, int64_t r0, int64_t r1, int64_t lo,
                                              const unsigned char* slot, int lane) {
-  const T* l = reinterpret_cast<const T*>(slot) + (r0 - lo) * w;
   T* g = static_cast<T*>(dst) + r0 * w;
   const int n = static_cast<int>((r1 - r0) * w);
-  for (int k = lane; k < n; k += WAVE) g[k] = l[k];
+  if (LS == 0 || LS == w) {
+    const T* l = reinterpret_cast<const T*>(slot) + (r0 - lo) * w;
+    for (int k = lane; k < n; k += WAVE) g[k] = l[k];
+  } else {
+    const T* l = reinterpret_cast<const T*>(slot) + (r0 - lo) * LS;
+    for (int k = lane; k < n; k += WAVE) g[k] = l[(k / w) * LS + k % w];
+  }
 }
 
 template <int K, class TIO>
@@ -165,18 +191,21 @@ __device__ __forceinline__ Inst<K> load_inst(const Level0Args& a, int64_t i) {
 
 // Source reading the wave's LDS slice: node i of the instance at global
 // row off is slice row off - lo + i.
-template <int K, int L, class TIO, int RHS, int OUT, int LRHS = RHS>
-__device__ __forceinline__ Src0<K, TIO, RHS> make_src0_lds(const Level0Args& a, int64_t i, int64_t off, int64_t n,
-                                                           int64_t lo, unsigned char* sl) {
-  using ST = Stage<K, L, TIO, LRHS, OUT>;   // slice layout of the variant LRHS
-  Src0<K, TIO, RHS> S;
+template <int K, int L, class TIO, int RHS, int OUT, class F, int LRHS = RHS>
+__device__ __forceinline__ Src0<K, TIO, RHS, F> make_src0_lds(const Level0Args& a, int64_t i, int64_t off,
+                                                              int64_t n, int64_t lo, unsigned char* sl) {
+  using ST = Stage<K, L, TIO, LRHS, OUT, F>;   // slice layout of the variant LRHS
+  Src0<K, TIO, RHS, F> S;
   S.c = reinterpret_cast<const TIO*>(sl + ST::C);
   S.s = reinterpret_cast<const TIO*>(sl + ST::S);
   S.d = reinterpret_cast<const TIO*>(sl + ST::D);
   S.g = reinterpret_cast<const TIO*>(sl + ST::G);
   S.v = reinterpret_cast<const TIO*>(sl + ST::V);
+  S.wg = reinterpret_cast<const TIO*>(sl + ST::WG);
+  S.wsm = reinterpret_cast<const TIO*>(sl + ST::WS);
+  S.wi = static_cast<const TIO*>(a.wi);
   S.u = static_cast<const TIO*>(a.u0);
-  S.uo = static_cast<int>(i) * a.t_init * a.n_init;
+  S.uo = static_cast<int>(i) * a.t_init * F::V * a.n_init;
   S.o = off - lo;
   S.n = n;
   S.p = load_inst<K, TIO>(a, i);
@@ -209,10 +238,9 @@ __device__ __forceinline__ void exchange_and_write(const Reduced<K>& red, bool w
 }
 
 // ------------------------------------------------------------ level 0 reduce
-template <int K, int L, class TIO, int RHS, bool WREC>
+template <int K, int L, class TIO, int RHS, bool WREC, class F>
 __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduce0(LevelDev l0, LevelDev l1, Level0Args a) {
-  constexpr int REC = Dim<K>::Q + Dim<K>::KK;
-  using ST = Stage<K, L, TIO, RHS, OUT_STORE>;
+  using ST = Stage<K, L, TIO, RHS, OUT_STORE, F>;
   extern __shared__ __align__(16) unsigned char smem[];
   unsigned char* sl = smem + (threadIdx.x / WAVE) * ST::BYTES;
   const int lane = lane_id();
@@ -232,8 +260,8 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduce0(LevelDev l0, Le
     const int64_t off = l0.node_off[inst];
     const int64_t n = l0.node_off[inst + 1] - off;
     const int64_t c1 = l1.chunk_off[inst];
-    const auto src = make_src0_lds<K, L, TIO, RHS, OUT_STORE>(a, inst, off, n, lo, sl);
-    stage_tile<K, L, TIO, RHS, OUT_STORE>(a, lo, hi, sl, lane);
+    const auto src = make_src0_lds<K, L, TIO, RHS, OUT_STORE, F>(a, inst, off, n, lo, sl);
+    stage_tile<K, L, TIO, RHS, OUT_STORE, F>(a, lo, hi, sl, lane);
     const int64_t j = gg - j0;
     const ChunkGeom geo = chunk_geom(j, n, L);
     Reduced<K> red;
@@ -347,11 +375,12 @@ struct Backsub0Waves {
   static constexpr int value = (K == 3 && L == 8 && OUT == OUT_GRAD) ? 2 : SMNN_MIN_WAVES;
 };
 
-template <int K, int L, class TIO, int RHS, int OUT>
+template <int K, int L, class TIO, int RHS, int OUT, class F>
 __global__ void __launch_bounds__(256, (Backsub0Waves<K, L, OUT>::value)) k_backsub0(LevelDev l0, LevelDev l1,
                                                                                      bool has_next, Level0Args a) {
   constexpr bool ADD = (RHS == RHS_RESID || RHS == RHS_GRESID);
-  using ST = Stage<K, L, TIO, RHS, OUT>;
+  constexpr int QE = F::QE, NI = F::V;   // governing equations per point; variables per initial point
+  using ST = Stage<K, L, TIO, RHS, OUT, F>;
   extern __shared__ __align__(16) unsigned char smem[];
   unsigned char* sl = smem + (threadIdx.x / WAVE) * ST::BYTES;
   const int lane = lane_id();
@@ -371,8 +400,8 @@ __global__ void __launch_bounds__(256, (Backsub0Waves<K, L, OUT>::value)) k_back
     const int64_t off = l0.node_off[inst];
     const int64_t n = l0.node_off[inst + 1] - off;
     const int64_t up0 = (has_next ? l1.node_off : l0.node_off)[inst];   // unconditional load
-    const auto src = make_src0_lds<K, L, TIO, RHS, OUT>(a, inst, off, n, lo, sl);
-    stage_tile<K, L, TIO, RHS, OUT>(a, lo, hi, sl, lane);
+    const auto src = make_src0_lds<K, L, TIO, RHS, OUT, F>(a, inst, off, n, lo, sl);
+    stage_tile<K, L, TIO, RHS, OUT, F>(a, lo, hi, sl, lane);
     const int64_t j = gg - j0;
     const int64_t up = has_next ? up0 : 0;
     const ChunkGeom geo = chunk_geom(j, n, L);
@@ -391,11 +420,14 @@ __global__ void __launch_bounds__(256, (Backsub0Waves<K, L, OUT>::value)) k_back
     const bool last_ends = __shfl(static_cast<int>(!geo.has_right), last, WAVE) != 0;
     __builtin_amdgcn_s_waitcnt(0);
     // Outputs go into the slice in place of inputs no lane reads afterwards
-    // (out / dc over c, dd over d, ds over s; a lane reads another lane's
-    // rows only for s, v, y of its left separator and v after its right
-    // one, before it writes anything), then out to HBM in whole rows.
+    // (out / dc over c, dd over d, ds over s, and the per-row weight
+    // gradients over their weights; a lane reads another lane's rows only
+    // for s, the smoothness weight, v and y of its left separator and v
+    // after its right one, before it writes anything), then out to HBM in
+    // whole rows.
     if (OUT == OUT_STORE && valid) {
-      StoreSink<TIO, ADD> sink{reinterpret_cast<TIO*>(sl + ST::C), vs, off - lo, off - lo};
+      // the solution goes over c, row for row (c rows hold QE K values)
+      StoreSink<TIO, ADD, QE * K> sink{reinterpret_cast<TIO*>(sl + ST::C), vs, off - lo, off - lo};
       if (geo.has_right) sink.template node<K>(geo.b + 1, xr);   // owned right separator
       const int fail = backsub_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
       if (fail) report_fail(a, inst, 0, geo.a + fail - 1);
@@ -412,8 +444,9 @@ __global__ void __launch_bounds__(256, (Backsub0Waves<K, L, OUT>::value)) k_back
       __builtin_amdgcn_s_waitcnt(0);
       __builtin_amdgcn_wave_barrier();
       if (valid) {
-        GradSink<K, TIO, ADD> sink;
+        GradSink<K, TIO, ADD, F> sink;
         sink.c = src.c; sink.d = src.d; sink.s = src.s;
+        sink.wg = src.wg; sink.wsm = src.wsm; sink.wi = src.wi;
         sink.y = reinterpret_cast<const TIO*>(sl + ST::Y);
         sink.v = vs;
         sink.o = off - lo;
@@ -421,7 +454,12 @@ __global__ void __launch_bounds__(256, (Backsub0Waves<K, L, OUT>::value)) k_back
         sink.dd = reinterpret_cast<TIO*>(sl + ST::D);
         sink.ds = reinterpret_cast<TIO*>(sl + ST::S);
         sink.oo = off - lo;
-        sink.du0 = static_cast<TIO*>(a.du0) + inst * a.t_init * a.n_init;
+        sink.du0 = static_cast<TIO*>(a.du0) + inst * a.t_init * NI * a.n_init;
+        if constexpr (F::WROW) {
+          sink.dwg = reinterpret_cast<TIO*>(sl + ST::WG);
+          sink.dws = reinterpret_cast<TIO*>(sl + ST::WS);
+          sink.dwi = static_cast<TIO*>(a.dwi) + inst * a.t_init * NI * a.n_init;
+        }
         sink.u = src.u;
         sink.uo = src.uo;
         sink.p = src.p;
@@ -429,22 +467,29 @@ __global__ void __launch_bounds__(256, (Backsub0Waves<K, L, OUT>::value)) k_back
         backsub_backward<K, L>(src, geo.a, geo.b, Ls, xs, sink);
         if (geo.has_left) sink.left(geo.a - 1, xl);
         if (!geo.has_right) {
-          sink.ds[sink.oo + n - 1] = static_cast<TIO>(0.0);   // s of the last point is unused
+          sink.last_point(n);   // the last point's step slot enters no row
           sink.zero_past_end(n);
         }
+        if constexpr (!F::WROW) {
 #pragma unroll
-        for (int e = 0; e < 3; ++e) a.dw_part[g * 3 + e] = sink.dw[e];
+          for (int e = 0; e < 3; ++e) a.dw_part[g * 3 + e] = sink.dw[e];
+        }
         if (fail) report_fail(a, inst, 0, geo.a + fail - 1);
       }
     }
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     if (OUT == OUT_STORE) {
-      unstage_rows<TIO>(a.out, K, r0, r1, lo, sl + ST::C, lane);
+      unstage_rows<TIO, QE * K>(a.out, K, r0, r1, lo, sl + ST::C, lane);
     } else {
-      unstage_rows<TIO>(a.dc, K, r0, r1, lo, sl + ST::C, lane);
-      unstage_rows<TIO>(a.dd, 1, r0, r1, lo, sl + ST::D, lane);
-      unstage_rows<TIO>(a.ds, 1, r0 - (first_starts ? 0 : 1), r1 - (last_ends ? 0 : 1), lo, sl + ST::S, lane);
+      const int64_t s0 = r0 - (first_starts ? 0 : 1), s1 = r1 - (last_ends ? 0 : 1);
+      unstage_rows<TIO>(a.dc, QE * K, r0, r1, lo, sl + ST::C, lane);
+      unstage_rows<TIO>(a.dd, QE, r0, r1, lo, sl + ST::D, lane);
+      unstage_rows<TIO>(a.ds, 1, s0, s1, lo, sl + ST::S, lane);
+      if constexpr (F::WROW) {
+        unstage_rows<TIO>(a.dwg, QE, r0, r1, lo, sl + ST::WG, lane);
+        unstage_rows<TIO>(a.dws, 1, s0, s1, lo, sl + ST::WS, lane);
+      }
     }
   }
 }
@@ -459,9 +504,9 @@ __global__ void __launch_bounds__(256, (Backsub0Waves<K, L, OUT>::value)) k_back
 // from the chunks on both of its sides) and lane 63 back-substitutes the
 // next tile's first chunk (the residual at a chunk's right separator needs
 // the iterate one step past it).
-template <int K, int L, class TIO, int RIN, int ROUT>
+template <int K, int L, class TIO, int RIN, int ROUT, class F>
 __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDev l0, LevelDev l1, Level0Args a) {
-  using ST = Stage<K, L, TIO, ROUT, OUT_STORE>;   // c, h, (b | dl/dy) staged; the iterate in the v slot
+  using ST = Stage<K, L, TIO, ROUT, OUT_STORE, F>;   // c, h, (b | dl/dy) staged; the iterate in the v slot
   constexpr int OWN = WAVE - 2;
   extern __shared__ __align__(16) unsigned char smem[];
   unsigned char* sl = smem + (threadIdx.x / WAVE) * ST::BYTES;
@@ -487,11 +532,12 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDe
     const int64_t n = l0.node_off[inst + 1] - off;
     const int64_t up0 = (l1.node_off ? l1.node_off : l0.node_off)[inst];
     const int64_t c1 = (l1.chunk_off ? l1.chunk_off : l0.chunk_off)[inst];
-    const auto src = make_src0_lds<K, L, TIO, RIN, OUT_STORE, ROUT>(a, inst, off, n, lo, sl);
-    stage_rows<TIO>(a.c, K, lo, hi, sl + ST::C, lane);
+    const auto src = make_src0_lds<K, L, TIO, RIN, OUT_STORE, F, ROUT>(a, inst, off, n, lo, sl);
+    stage_rows<TIO>(a.c, F::QE * K, lo, hi, sl + ST::C, lane);
     stage_rows<TIO>(a.s, 1, lo, hi, sl + ST::S, lane);
-    if (RIN == RHS_BETA) stage_rows<TIO>(a.d, 1, lo, hi, sl + ST::D, lane);
+    if (RIN == RHS_BETA) stage_rows<TIO>(a.d, F::QE, lo, hi, sl + ST::D, lane);
     if (RIN == RHS_G) stage_rows<TIO>(a.g, K, lo, hi, sl + ST::G, lane);
+    stage_weights<K, L, TIO, ROUT, OUT_STORE, F>(a, lo, hi, sl, lane);
     const int64_t j = gg - j0;
     const ChunkGeom geo = chunk_geom(j, n, L);
     double xl[K], xr[K], xs[L][K];
@@ -524,8 +570,9 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDe
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     // 2. reduce with the residual of that iterate as right-hand side
-    Src0<K, TIO, ROUT> rs;
+    Src0<K, TIO, ROUT, F> rs;
     rs.c = src.c; rs.d = src.d; rs.s = src.s; rs.g = src.g; rs.v = it;
+    rs.wg = src.wg; rs.wsm = src.wsm; rs.wi = src.wi;
     rs.n = src.n; rs.o = src.o; rs.p = src.p; rs.u = src.u; rs.uo = src.uo;
     Reduced<K> red;
 #pragma unroll
@@ -767,9 +814,9 @@ int64_t grid_for(int64_t tiles, const Launch& cfg) {
 
 // Grid, workgroup and dynamic LDS of a level-0 launch: as many waves per
 // workgroup as cfg.block asks for and the per-workgroup LDS limit allows.
-template <int K, int L, class TIO, int RHS, int OUT>
+template <int K, int L, class TIO, int RHS, int OUT, class F>
 bool level0_grid(int64_t tiles, const Launch& cfg, dim3& grid, dim3& block, size_t& lds) {
-  constexpr size_t wb = Stage<K, L, TIO, RHS, OUT>::BYTES;
+  constexpr size_t wb = Stage<K, L, TIO, RHS, OUT, F>::BYTES;
   const int64_t fit = static_cast<int64_t>(cfg.lds_max) / static_cast<int64_t>(wb);
   if (fit < 1) return false;
   int wpb = cfg.block / WAVE;
@@ -783,107 +830,109 @@ bool level0_grid(int64_t tiles, const Launch& cfg, dim3& grid, dim3& block, size
   return true;
 }
 
-template <int K, int L, class TIO, int RHS, bool WREC>
+template <int K, int L, class TIO, int RHS, bool WREC, class F>
 hipError_t launch_r0(const LevelDev& l0, const LevelDev& l1, const Level0Args& a, const Launch& cfg,
                      hipStream_t st) {
   const int64_t tiles = l0.chunks > 1 ? (l0.chunks - 2) / (WAVE - 1) + 1 : 1;
   dim3 grid, block;
   size_t lds;
-  if (!level0_grid<K, L, TIO, RHS, OUT_STORE>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
+  if (!level0_grid<K, L, TIO, RHS, OUT_STORE, F>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
   Level0Args b = a;
   b.wpb = static_cast<int>(block.x) / WAVE;
   b.nwaves = static_cast<int64_t>(grid.x) * b.wpb;
-  hipLaunchKernelGGL((k_reduce0<K, L, TIO, RHS, WREC>), grid, block, lds, st, l0, l1, b);
+  hipLaunchKernelGGL((k_reduce0<K, L, TIO, RHS, WREC, F>), grid, block, lds, st, l0, l1, b);
   return hipGetLastError();
 }
 
-template <int K, int L, class TIO, int RHS, int OUT>
+template <int K, int L, class TIO, int RHS, int OUT, class F>
 hipError_t launch_b0(const LevelDev& l0, const LevelDev* l1, const Level0Args& a, const Launch& cfg,
                      hipStream_t st) {
   const int64_t tiles = (l0.chunks + WAVE - 1) / WAVE;
   dim3 grid, block;
   size_t lds;
-  if (!level0_grid<K, L, TIO, RHS, OUT>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
+  if (!level0_grid<K, L, TIO, RHS, OUT, F>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
   const LevelDev nx = l1 ? *l1 : LevelDev{};
   Level0Args b = a;
   b.wpb = static_cast<int>(block.x) / WAVE;
   b.nwaves = static_cast<int64_t>(grid.x) * b.wpb;
-  hipLaunchKernelGGL((k_backsub0<K, L, TIO, RHS, OUT>), grid, block, lds, st, l0, nx, l1 != nullptr, b);
+  hipLaunchKernelGGL((k_backsub0<K, L, TIO, RHS, OUT, F>), grid, block, lds, st, l0, nx, l1 != nullptr, b);
   return hipGetLastError();
 }
 
-template <int K, int L, class TIO, int RIN, int ROUT>
+template <int K, int L, class TIO, int RIN, int ROUT, class F>
 hipError_t launch_br0(const LevelDev& l0, const LevelDev& l1, const Level0Args& a, const Launch& cfg,
                       hipStream_t st) {
   const int64_t tiles = (l0.chunks + WAVE - 3) / (WAVE - 2);
   dim3 grid, block;
   size_t lds;
-  if (!level0_grid<K, L, TIO, ROUT, OUT_STORE>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
+  if (!level0_grid<K, L, TIO, ROUT, OUT_STORE, F>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
   Level0Args b = a;
   b.wpb = static_cast<int>(block.x) / WAVE;
   b.nwaves = static_cast<int64_t>(grid.x) * b.wpb;
-  hipLaunchKernelGGL((k_backsub_reduce0<K, L, TIO, RIN, ROUT>), grid, block, lds, st, l0, l1, b);
+  hipLaunchKernelGGL((k_backsub_reduce0<K, L, TIO, RIN, ROUT, F>), grid, block, lds, st, l0, l1, b);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------- dispatchers
-template <int K, int L, class TIO>
+template <int K, int L, class TIO, class F>
 hipError_t reduce0_t(int rhs, bool wrec, const LevelDev& l0, const LevelDev& l1, const Level0Args& a,
                      const Launch& cfg, hipStream_t st) {
   switch (rhs) {
     case RHS_BETA:
-      return wrec ? launch_r0<K, L, TIO, RHS_BETA, true>(l0, l1, a, cfg, st)
-                  : launch_r0<K, L, TIO, RHS_BETA, false>(l0, l1, a, cfg, st);
-    case RHS_RESID: return launch_r0<K, L, TIO, RHS_RESID, false>(l0, l1, a, cfg, st);
+      return wrec ? launch_r0<K, L, TIO, RHS_BETA, true, F>(l0, l1, a, cfg, st)
+                  : launch_r0<K, L, TIO, RHS_BETA, false, F>(l0, l1, a, cfg, st);
+    case RHS_RESID: return launch_r0<K, L, TIO, RHS_RESID, false, F>(l0, l1, a, cfg, st);
     case RHS_G:
-      return wrec ? launch_r0<K, L, TIO, RHS_G, true>(l0, l1, a, cfg, st)
-                  : launch_r0<K, L, TIO, RHS_G, false>(l0, l1, a, cfg, st);
-    case RHS_GRESID: return launch_r0<K, L, TIO, RHS_GRESID, false>(l0, l1, a, cfg, st);
+      return wrec ? launch_r0<K, L, TIO, RHS_G, true, F>(l0, l1, a, cfg, st)
+                  : launch_r0<K, L, TIO, RHS_G, false, F>(l0, l1, a, cfg, st);
+    case RHS_GRESID: return launch_r0<K, L, TIO, RHS_GRESID, false, F>(l0, l1, a, cfg, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int K, int L, class TIO>
+template <int K, int L, class TIO, class F>
 hipError_t backsub0_t(int rhs, int out, const LevelDev& l0, const LevelDev* l1, const Level0Args& a,
                       const Launch& cfg, hipStream_t st) {
   if (out == OUT_STORE) {
     switch (rhs) {
-      case RHS_BETA: return launch_b0<K, L, TIO, RHS_BETA, OUT_STORE>(l0, l1, a, cfg, st);
-      case RHS_RESID: return launch_b0<K, L, TIO, RHS_RESID, OUT_STORE>(l0, l1, a, cfg, st);
-      case RHS_G: return launch_b0<K, L, TIO, RHS_G, OUT_STORE>(l0, l1, a, cfg, st);
-      case RHS_GRESID: return launch_b0<K, L, TIO, RHS_GRESID, OUT_STORE>(l0, l1, a, cfg, st);
+      case RHS_BETA: return launch_b0<K, L, TIO, RHS_BETA, OUT_STORE, F>(l0, l1, a, cfg, st);
+      case RHS_RESID: return launch_b0<K, L, TIO, RHS_RESID, OUT_STORE, F>(l0, l1, a, cfg, st);
+      case RHS_G: return launch_b0<K, L, TIO, RHS_G, OUT_STORE, F>(l0, l1, a, cfg, st);
+      case RHS_GRESID: return launch_b0<K, L, TIO, RHS_GRESID, OUT_STORE, F>(l0, l1, a, cfg, st);
       default: return hipErrorInvalidValue;
     }
   }
   switch (rhs) {
-    case RHS_G: return launch_b0<K, L, TIO, RHS_G, OUT_GRAD>(l0, l1, a, cfg, st);
-    case RHS_GRESID: return launch_b0<K, L, TIO, RHS_GRESID, OUT_GRAD>(l0, l1, a, cfg, st);
+    case RHS_G: return launch_b0<K, L, TIO, RHS_G, OUT_GRAD, F>(l0, l1, a, cfg, st);
+    case RHS_GRESID: return launch_b0<K, L, TIO, RHS_GRESID, OUT_GRAD, F>(l0, l1, a, cfg, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int K, int L, class TIO>
+template <int K, int L, class TIO, class F>
 hipError_t backsub_reduce0_t(int rhs_in, const LevelDev& l0, const LevelDev& l1, const Level0Args& a,
                              const Launch& cfg, hipStream_t st) {
   switch (rhs_in) {
-    case RHS_BETA: return launch_br0<K, L, TIO, RHS_BETA, RHS_RESID>(l0, l1, a, cfg, st);
-    case RHS_G: return launch_br0<K, L, TIO, RHS_G, RHS_GRESID>(l0, l1, a, cfg, st);
+    case RHS_BETA: return launch_br0<K, L, TIO, RHS_BETA, RHS_RESID, F>(l0, l1, a, cfg, st);
+    case RHS_G: return launch_br0<K, L, TIO, RHS_G, RHS_GRESID, F>(l0, l1, a, cfg, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int K, int L, class TIO>
+template <int K, int L, class TIO, class F>
 size_t lds_bytes_t(int rhs, int out) {
   if (out == OUT_GRAD)
-    return rhs == RHS_GRESID ? Stage<K, L, TIO, RHS_GRESID, OUT_GRAD>::BYTES : Stage<K, L, TIO, RHS_G, OUT_GRAD>::BYTES;
+    return rhs == RHS_GRESID ? Stage<K, L, TIO, RHS_GRESID, OUT_GRAD, F>::BYTES
+                             : Stage<K, L, TIO, RHS_G, OUT_GRAD, F>::BYTES;
   switch (rhs) {
-    case RHS_BETA: return Stage<K, L, TIO, RHS_BETA, OUT_STORE>::BYTES;
-    case RHS_RESID: return Stage<K, L, TIO, RHS_RESID, OUT_STORE>::BYTES;
-    case RHS_G: return Stage<K, L, TIO, RHS_G, OUT_STORE>::BYTES;
-    default: return Stage<K, L, TIO, RHS_GRESID, OUT_STORE>::BYTES;
+    case RHS_BETA: return Stage<K, L, TIO, RHS_BETA, OUT_STORE, F>::BYTES;
+    case RHS_RESID: return Stage<K, L, TIO, RHS_RESID, OUT_STORE, F>::BYTES;
+    case RHS_G: return Stage<K, L, TIO, RHS_G, OUT_STORE, F>::BYTES;
+    default: return Stage<K, L, TIO, RHS_GRESID, OUT_STORE, F>::BYTES;
   }
 }
 
+#if SMNN_TU_FORMS == 0
 template <int K, int L>
 hipError_t reduceN_t(bool wrec, int level, const LevelDev& l, const LevelDev& nx, const Level0Args& a,
                      const Launch& cfg, hipStream_t st) {
@@ -930,12 +979,20 @@ hipError_t top_t(int level, const LevelDev& l, const Level0Args& a, const Launch
   hipLaunchKernelGGL((k_top<K, L>), grid, block, wb * wpb, st, l, b, level);
   return hipGetLastError();
 }
+#endif
 
 }  // namespace
 
-// (K, L) pairs compiled in: L is the chunk length of every level.
-#ifdef SMNN_FOR_EACH_KL
-#elif SMNN_TU_K == 2
+// What this translation unit compiles in.
+//   SMNN_FOR_EACH_KL(X):    (K, L) pairs of the separator levels (X(K, L)),
+//                           SMNN_TU_FORMS == 0 only;
+//   SMNN_FOR_EACH_KLF(X):   level-0 (K, L, instance form, form id) tuples,
+//                           form ids as in smnn_internal.h (SMNN_FORM_*).
+// SMNN_TU_FORMS == 0 holds the scalar form (one variable, one governing
+// equation, three scalar weights) and the separator levels; 1 the scalar
+// shape with per-row weights; 2 two coupled variables (block size 4).
+#if SMNN_TU_FORMS == 0
+#if SMNN_TU_K == 2
 #define SMNN_FOR_EACH_KL(X) X(2, 8) X(2, 16)
 #elif SMNN_TU_K == 3
 #define SMNN_FOR_EACH_KL(X) X(3, 4) X(3, 8) X(3, 16)
@@ -944,55 +1001,88 @@ hipError_t top_t(int level, const LevelDev& l, const Level0Args& a, const Launch
 #elif SMNN_TU_K == 5
 #define SMNN_FOR_EACH_KL(X) X(5, 4)
 #endif
+#define SMNN_X_SCALAR(KV, LV) X(KV, LV, FormScalar, SMNN_FORM_SCALAR)
+#define SMNN_FOR_EACH_KLF(X) SMNN_FOR_EACH_KL(SMNN_X_SCALAR)
+#elif SMNN_TU_FORMS == 1
+using FormRows = Form<1, 1, true>;
+#if SMNN_TU_K == 2
+#define SMNN_FOR_EACH_KLF(X) X(2, 8, FormRows, SMNN_FORM_ROWS)
+#elif SMNN_TU_K == 3
+#define SMNN_FOR_EACH_KLF(X) X(3, 4, FormRows, SMNN_FORM_ROWS) X(3, 8, FormRows, SMNN_FORM_ROWS)
+#elif SMNN_TU_K == 4
+#define SMNN_FOR_EACH_KLF(X) X(4, 4, FormRows, SMNN_FORM_ROWS) X(4, 8, FormRows, SMNN_FORM_ROWS)
+#elif SMNN_TU_K == 5
+#define SMNN_FOR_EACH_KLF(X) X(5, 4, FormRows, SMNN_FORM_ROWS)
+#endif
+#elif SMNN_TU_FORMS == 2
+#if SMNN_TU_K != 4
+#error "two coupled variables of order 1 have block size 4"
+#endif
+using FormV2 = Form<2, 2, false>;
+using FormV2Rows = Form<2, 2, true>;
+using FormV2Q1 = Form<2, 1, false>;
+#define SMNN_FOR_EACH_KLF(X)                                                                 \
+  X(4, 4, FormV2, SMNN_FORM_V2) X(4, 8, FormV2, SMNN_FORM_V2)                                \
+  X(4, 4, FormV2Rows, SMNN_FORM_V2_ROWS) X(4, 8, FormV2Rows, SMNN_FORM_V2_ROWS)              \
+  X(4, 4, FormV2Q1, SMNN_FORM_V2_Q1) X(4, 8, FormV2Q1, SMNN_FORM_V2_Q1)
+#endif
 
+bool SMNN_KFN(supported0)(int K, int L, int form) {
+#define X(KV, LV, FT, FID) if (K == KV && L == LV && form == FID) return true;
+  SMNN_FOR_EACH_KLF(X)
+#undef X
+  return false;
+}
+
+size_t SMNN_KFN(level0_lds_bytes)(int K, int L, int form, bool f32, int rhs_mode, int out_mode) {
+#define X(KV, LV, FT, FID)                                                                                   \
+  if (K == KV && L == LV && form == FID)                                                                     \
+    return f32 ? lds_bytes_t<KV, LV, float, FT>(rhs_mode, out_mode) : lds_bytes_t<KV, LV, double, FT>(rhs_mode, out_mode);
+  SMNN_FOR_EACH_KLF(X)
+#undef X
+  return 0;
+}
+
+hipError_t SMNN_KFN(launch_reduce0)(int K, int L, int form, bool f32, int rhs_mode, bool write_rec, const LevelDev& l0,
+                                    const LevelDev& l1, const Level0Args& a, const Launch& cfg, hipStream_t st) {
+#define X(KV, LV, FT, FID)                                                                           \
+  if (K == KV && L == LV && form == FID)                                                             \
+    return f32 ? reduce0_t<KV, LV, float, FT>(rhs_mode, write_rec, l0, l1, a, cfg, st)              \
+               : reduce0_t<KV, LV, double, FT>(rhs_mode, write_rec, l0, l1, a, cfg, st);
+  SMNN_FOR_EACH_KLF(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t SMNN_KFN(launch_backsub0)(int K, int L, int form, bool f32, int rhs_mode, int out_mode, const LevelDev& l0,
+                                     const LevelDev* l1, const Level0Args& a, const Launch& cfg, hipStream_t st) {
+#define X(KV, LV, FT, FID)                                                                           \
+  if (K == KV && L == LV && form == FID)                                                             \
+    return f32 ? backsub0_t<KV, LV, float, FT>(rhs_mode, out_mode, l0, l1, a, cfg, st)              \
+               : backsub0_t<KV, LV, double, FT>(rhs_mode, out_mode, l0, l1, a, cfg, st);
+  SMNN_FOR_EACH_KLF(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t SMNN_KFN(launch_backsub_reduce0)(int K, int L, int form, bool f32, int rhs_in, const LevelDev& l0,
+                                            const LevelDev& l1, const Level0Args& a, const Launch& cfg,
+                                            hipStream_t st) {
+#define X(KV, LV, FT, FID)                                                                           \
+  if (K == KV && L == LV && form == FID)                                                             \
+    return f32 ? backsub_reduce0_t<KV, LV, float, FT>(rhs_in, l0, l1, a, cfg, st)                   \
+               : backsub_reduce0_t<KV, LV, double, FT>(rhs_in, l0, l1, a, cfg, st);
+  SMNN_FOR_EACH_KLF(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+#if SMNN_TU_FORMS == 0
 bool SMNN_KFN(supported)(int K, int L) {
 #define X(KV, LV) if (K == KV && L == LV) return true;
   SMNN_FOR_EACH_KL(X)
 #undef X
   return false;
-}
-
-size_t SMNN_KFN(level0_lds_bytes)(int K, int L, bool f32, int rhs_mode, int out_mode) {
-#define X(KV, LV)                                                                                    \
-  if (K == KV && L == LV)                                                                            \
-    return f32 ? lds_bytes_t<KV, LV, float>(rhs_mode, out_mode) : lds_bytes_t<KV, LV, double>(rhs_mode, out_mode);
-  SMNN_FOR_EACH_KL(X)
-#undef X
-  return 0;
-}
-
-hipError_t SMNN_KFN(launch_reduce0)(int K, int L, bool f32, int rhs_mode, bool write_rec, const LevelDev& l0,
-                          const LevelDev& l1, const Level0Args& a, const Launch& cfg, hipStream_t st) {
-#define X(KV, LV)                                                                                    \
-  if (K == KV && L == LV)                                                                            \
-    return f32 ? reduce0_t<KV, LV, float>(rhs_mode, write_rec, l0, l1, a, cfg, st)                  \
-               : reduce0_t<KV, LV, double>(rhs_mode, write_rec, l0, l1, a, cfg, st);
-  SMNN_FOR_EACH_KL(X)
-#undef X
-  return hipErrorInvalidValue;
-}
-
-hipError_t SMNN_KFN(launch_backsub0)(int K, int L, bool f32, int rhs_mode, int out_mode, const LevelDev& l0,
-                           const LevelDev* l1, const Level0Args& a, const Launch& cfg, hipStream_t st) {
-#define X(KV, LV)                                                                                    \
-  if (K == KV && L == LV)                                                                            \
-    return f32 ? backsub0_t<KV, LV, float>(rhs_mode, out_mode, l0, l1, a, cfg, st)                  \
-               : backsub0_t<KV, LV, double>(rhs_mode, out_mode, l0, l1, a, cfg, st);
-  SMNN_FOR_EACH_KL(X)
-#undef X
-  return hipErrorInvalidValue;
-}
-
-hipError_t SMNN_KFN(launch_backsub_reduce0)(int K, int L, bool f32, int rhs_in, const LevelDev& l0,
-                                            const LevelDev& l1, const Level0Args& a, const Launch& cfg,
-                                            hipStream_t st) {
-#define X(KV, LV)                                                                                    \
-  if (K == KV && L == LV)                                                                            \
-    return f32 ? backsub_reduce0_t<KV, LV, float>(rhs_in, l0, l1, a, cfg, st)                       \
-               : backsub_reduce0_t<KV, LV, double>(rhs_in, l0, l1, a, cfg, st);
-  SMNN_FOR_EACH_KL(X)
-#undef X
-  return hipErrorInvalidValue;
 }
 
 hipError_t SMNN_KFN(launch_reduceN)(int K, int L, bool write_rec, int level, const LevelDev& l, const LevelDev& lnext,
@@ -1029,5 +1119,6 @@ hipError_t SMNN_KFN(launch_top)(int K, int L, int level, const LevelDev& l, cons
 #undef X
   return hipErrorInvalidValue;
 }
+#endif
 
 }  // namespace smnn

@@ -68,27 +68,35 @@ hipError_t launch_info_finalize(const Level0Args& a, int32_t* info, hipStream_t 
   return hipGetLastError();
 }
 
-// Dispatch on the block size to the per-K translation units.
-#define SMNN_DECL(KV)                                                                                   \
-  bool supported_k##KV(int, int);                                                                       \
-  hipError_t launch_reduce0_k##KV(int, int, bool, int, bool, const LevelDev&, const LevelDev&,           \
+// Dispatch on the block size (and, at level 0, the instance form) to the
+// translation units of smnn_kernels.hip: _k<K> holds the separator levels
+// and the scalar form, _k<K>f1 per-row weights, _k4f2 two coupled variables.
+#define SMNN_DECL0(SUF)                                                                                 \
+  bool supported0_##SUF(int, int, int);                                                                 \
+  hipError_t launch_reduce0_##SUF(int, int, int, bool, int, bool, const LevelDev&, const LevelDev&,      \
                                   const Level0Args&, const Launch&, hipStream_t);                        \
-  hipError_t launch_backsub0_k##KV(int, int, bool, int, int, const LevelDev&, const LevelDev*,           \
+  hipError_t launch_backsub0_##SUF(int, int, int, bool, int, int, const LevelDev&, const LevelDev*,      \
                                    const Level0Args&, const Launch&, hipStream_t);                       \
+  size_t level0_lds_bytes_##SUF(int, int, int, bool, int, int);                                           \
+  hipError_t launch_backsub_reduce0_##SUF(int, int, int, bool, int, const LevelDev&, const LevelDev&,     \
+                                          const Level0Args&, const Launch&, hipStream_t);
+#define SMNN_DECL(KV)                                                                                   \
+  SMNN_DECL0(k##KV)                                                                                     \
+  SMNN_DECL0(k##KV##f1)                                                                                 \
+  bool supported_k##KV(int, int);                                                                       \
   hipError_t launch_reduceN_k##KV(int, int, bool, int, const LevelDev&, const LevelDev&, const Level0Args&, \
                                   const Launch&, hipStream_t);                                           \
   hipError_t launch_backsubN_k##KV(int, int, int, const LevelDev&, const LevelDev*, const Level0Args&,    \
                                    const Launch&, hipStream_t);                                          \
-  size_t level0_lds_bytes_k##KV(int, int, bool, int, int);                                                \
-  hipError_t launch_backsub_reduce0_k##KV(int, int, bool, int, const LevelDev&, const LevelDev&,          \
-                                          const Level0Args&, const Launch&, hipStream_t);                \
   size_t top_lds_bytes_k##KV(int, int);                                                                   \
   hipError_t launch_top_k##KV(int, int, int, const LevelDev&, const Level0Args&, const Launch&, hipStream_t);
 SMNN_DECL(2)
 SMNN_DECL(3)
 SMNN_DECL(4)
 SMNN_DECL(5)
+SMNN_DECL0(k4f2)
 #undef SMNN_DECL
+#undef SMNN_DECL0
 
 #define SMNN_SWITCH(FN, ...)                     \
   switch (K) {                                   \
@@ -98,31 +106,51 @@ SMNN_DECL(5)
     case 5: return FN##_k5(__VA_ARGS__);         \
   }
 
+// level-0 functions: by form group, then block size
+#define SMNN_SWITCH0(FN, ...)                                          \
+  if (form == SMNN_FORM_SCALAR) {                                      \
+    SMNN_SWITCH(FN, __VA_ARGS__)                                       \
+  } else if (form == SMNN_FORM_ROWS) {                                 \
+    switch (K) {                                                       \
+      case 2: return FN##_k2f1(__VA_ARGS__);                           \
+      case 3: return FN##_k3f1(__VA_ARGS__);                           \
+      case 4: return FN##_k4f1(__VA_ARGS__);                           \
+      case 5: return FN##_k5f1(__VA_ARGS__);                           \
+    }                                                                  \
+  } else if (K == 4) {                                                 \
+    return FN##_k4f2(__VA_ARGS__);                                     \
+  }
+
 bool supported(int K, int L) {
   SMNN_SWITCH(supported, K, L)
   return false;
 }
 
-size_t level0_lds_bytes(int K, int L, bool f32, int rhs_mode, int out_mode) {
-  SMNN_SWITCH(level0_lds_bytes, K, L, f32, rhs_mode, out_mode)
+bool supported0(int K, int L, int form) {
+  SMNN_SWITCH0(supported0, K, L, form)
+  return false;
+}
+
+size_t level0_lds_bytes(int K, int L, int form, bool f32, int rhs_mode, int out_mode) {
+  SMNN_SWITCH0(level0_lds_bytes, K, L, form, f32, rhs_mode, out_mode)
   return 0;
 }
 
-hipError_t launch_reduce0(int K, int L, bool f32, int rhs_mode, bool write_rec, const LevelDev& l0,
+hipError_t launch_reduce0(int K, int L, int form, bool f32, int rhs_mode, bool write_rec, const LevelDev& l0,
                           const LevelDev& l1, const Level0Args& a, const Launch& cfg, hipStream_t st) {
-  SMNN_SWITCH(launch_reduce0, K, L, f32, rhs_mode, write_rec, l0, l1, a, cfg, st)
+  SMNN_SWITCH0(launch_reduce0, K, L, form, f32, rhs_mode, write_rec, l0, l1, a, cfg, st)
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_backsub0(int K, int L, bool f32, int rhs_mode, int out_mode, const LevelDev& l0,
+hipError_t launch_backsub0(int K, int L, int form, bool f32, int rhs_mode, int out_mode, const LevelDev& l0,
                            const LevelDev* l1, const Level0Args& a, const Launch& cfg, hipStream_t st) {
-  SMNN_SWITCH(launch_backsub0, K, L, f32, rhs_mode, out_mode, l0, l1, a, cfg, st)
+  SMNN_SWITCH0(launch_backsub0, K, L, form, f32, rhs_mode, out_mode, l0, l1, a, cfg, st)
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_backsub_reduce0(int K, int L, bool f32, int rhs_in, const LevelDev& l0, const LevelDev& l1,
-                                  const Level0Args& a, const Launch& cfg, hipStream_t st) {
-  SMNN_SWITCH(launch_backsub_reduce0, K, L, f32, rhs_in, l0, l1, a, cfg, st)
+hipError_t launch_backsub_reduce0(int K, int L, int form, bool f32, int rhs_in, const LevelDev& l0,
+                                  const LevelDev& l1, const Level0Args& a, const Launch& cfg, hipStream_t st) {
+  SMNN_SWITCH0(launch_backsub_reduce0, K, L, form, f32, rhs_in, l0, l1, a, cfg, st)
   return hipErrorInvalidValue;
 }
 

@@ -22,7 +22,12 @@ class Plan:
 
     steps: int (every instance has that many steps) or a sequence of T_i.
     init_points: T_init, the leading time points that carry the n_init
-           initial values (u0 is then N x T_init x n_init).
+           initial values (u0 is then N x T_init x V x n_init).
+    variables, equations: V coupled variables and Q governing equations
+           per time point (c is S x Q x V(R+1), b is S x Q, y is S x V(R+1)).
+    row_weights: w holds one weight per row (the governing weights [S][Q],
+           the initial weights [N][T_init][V][n_init] and the smoothness
+           weights [S], concatenated) instead of three per instance.
     mode:  'fp64' (the paper's single solve), 'fp64r' (plus row-residual
            refinement) or 'fp32r' (float32 memory traffic, float64 arithmetic,
            refinement).
@@ -30,7 +35,8 @@ class Plan:
 
     def __init__(self, order: int, n_init: int, n_inst: int, steps, mode: str = "fp64r",
                  refine_steps: int = -1, chunk: int = 0, block: int = 0, max_blocks: int = 0,
-                 chunk_upper: int = 0, init_points: int = 1):
+                 chunk_upper: int = 0, init_points: int = 1, variables: int = 1, equations: int = 0,
+                 row_weights: bool = False):
         L = _lib.lib()
         if mode not in _lib.MODES:
             raise ValueError("mode must be one of %s" % sorted(_lib.MODES))
@@ -51,12 +57,16 @@ class Plan:
         d.chunk_upper = int(chunk_upper)
         d.block, d.max_blocks = int(block), int(max_blocks)
         d.init_points = int(init_points)
+        d.variables, d.equations, d.row_weights = int(variables), int(equations), int(bool(row_weights))
         h = ctypes.c_void_p()
         _lib.check(L.smnn_plan_create(ctypes.byref(d), ctypes.byref(h)), "smnn_plan_create")
         self._h = h
         self._L = L
         self.order, self.n_init, self.n_inst, self.mode = int(order), int(n_init), int(n_inst), mode
-        self.k = self.order + 1
+        self.variables = int(variables)
+        self.equations = int(equations) if equations else self.variables
+        self.row_weights = bool(row_weights)
+        self.k = self.variables * (self.order + 1)     # unknowns per time point
         self.init_points = self.query(_lib.Q_INIT_POINTS)
         fb, wb, S = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int64()
         _lib.check(L.smnn_plan_sizes(h, ctypes.byref(fb), ctypes.byref(wb), ctypes.byref(S)), "smnn_plan_sizes")
@@ -129,14 +139,26 @@ class Plan:
         if t.numel() != int(np.prod(shape)):
             raise ValueError("%s has %d elements, expected %s" % (name, t.numel(), shape))
 
+    @property
+    def n_initial(self):
+        """Initial values per instance: T_init V n_init."""
+        return self.init_points * self.variables * self.n_init
+
+    @property
+    def weight_shape(self):
+        """Elements of w (and dw): (N, 3), or the per-row buffer's length."""
+        if self.row_weights:
+            return (self.total_steps * self.equations + self.n_inst * self.n_initial + self.total_steps,)
+        return (self.n_inst, 3)
+
     def _check_inputs(self, c, b, h, u0, w):
-        S, k, N = self.total_steps, self.k, self.n_inst
-        self._check("c", c, (S, k))
-        self._check("b", b, (S,))
+        S, k, N, Q = self.total_steps, self.k, self.n_inst, self.equations
+        self._check("c", c, (S, Q * k))
+        self._check("b", b, (S * Q,))
         self._check("h", h, (S,))
         if self.n_init:
-            self._check("u0", u0, (N, self.init_points, self.n_init))
-        self._check("w", w, (N, 3))
+            self._check("u0", u0, (N, self.n_initial))
+        self._check("w", w, self.weight_shape)
 
     def forward(self, c, b, h, u0, w, y, factor, workspace, info=None, stream=None):
         """Enqueue smnn_forward on `stream` (default: torch's current stream)."""
@@ -161,11 +183,12 @@ class Plan:
         """Enqueue smnn_backward on `stream` (default: torch's current stream)."""
         self._check_inputs(c, b, h, u0, w)
         S, k, N = self.total_steps, self.k, self.n_inst
-        for name, t, shape in (("y", y, (S, k)), ("gy", gy, (S, k)), ("dc", dc, (S, k)), ("db", db, (S,)),
-                               ("dh", dh, (S,)), ("dw", dw, (N, 3))):
+        Q = self.equations
+        for name, t, shape in (("y", y, (S, k)), ("gy", gy, (S, k)), ("dc", dc, (S, Q * k)), ("db", db, (S * Q,)),
+                               ("dh", dh, (S,)), ("dw", dw, self.weight_shape)):
             self._check(name, t, shape)
         if self.n_init:
-            self._check("du0", du0, (N, self.init_points, self.n_init))
+            self._check("du0", du0, (N, self.n_initial))
         st = torch.cuda.current_stream(c.device).cuda_stream if stream is None else stream
         _lib.check(self._L.smnn_backward(self._h, _ptr(c), _ptr(b), _ptr(h), _ptr(u0), _ptr(w), _ptr(y),
                                          _ptr(factor), factor.numel(), _ptr(gy), _ptr(dc), _ptr(db), _ptr(dh),
@@ -176,14 +199,16 @@ class Plan:
 _PLANS: "OrderedDict[tuple, Plan]" = OrderedDict()
 
 
-def get_plan(order, n_init, n_inst, steps, mode="fp64r", refine_steps=-1, chunk=0, init_points=1):
+def get_plan(order, n_init, n_inst, steps, mode="fp64r", refine_steps=-1, chunk=0, init_points=1, variables=1,
+             equations=0, row_weights=False):
     """Plans are cached per (device, sizes, mode); creating one uploads metadata."""
     key_steps = int(steps) if np.isscalar(steps) else tuple(int(t) for t in steps)
-    key = (torch.cuda.current_device(), order, n_init, n_inst, key_steps, mode, refine_steps, chunk, init_points)
+    key = (torch.cuda.current_device(), order, n_init, n_inst, key_steps, mode, refine_steps, chunk, init_points,
+           variables, equations, bool(row_weights))
     p = _PLANS.get(key)
     if p is None:
         p = Plan(order, n_init, n_inst, steps, mode=mode, refine_steps=refine_steps, chunk=chunk,
-                 init_points=init_points)
+                 init_points=init_points, variables=variables, equations=equations, row_weights=row_weights)
         _PLANS[key] = p
         while len(_PLANS) > 16:
             _PLANS.popitem(last=False)
@@ -222,30 +247,36 @@ class SmnnSolve(torch.autograd.Function):
         return dc, db, dh, du0, dw, None
 
 
-def solve(c, b, h, u0, w, order=None, n_init=None, steps=None, mode="fp64r", refine_steps=-1, chunk=0):
+def solve(c, b, h, u0, w, order=None, n_init=None, steps=None, mode="fp64r", refine_steps=-1, chunk=0,
+          variables=1, equations=0, row_weights=False, init_points=None):
     """Differentiable batched solve.
 
-    Uniform batches may pass c as (N, T, R+1), b and h as (N, T); otherwise c is
-    (S, R+1), b and h are (S,) and `steps` lists T_i.  u0 is (N, n_init)
-    (initial values at the first point) or (N, T_init, n_init) (at each of the
-    first T_init points); w is (N, 3).  Returns y with the shape of c.
+    Uniform one-variable batches may pass c as (N, T, R+1), b and h as (N, T);
+    otherwise c is (S, Q V (R+1)), b is (S, Q) or (S,), h is (S,) and `steps`
+    lists T_i (or is the uniform T).  u0 is (N, n_init) (initial values at the
+    first point) or (N, T_init, n_init) (at each of the first T_init points)
+    for one variable, (N, T_init V n_init) in general; w is (N, 3), or with
+    row_weights the per-row buffer described in Plan.  Returns y with the
+    shape of c (one variable) or (S, V (R+1)).
     """
     shape = c.shape
-    if c.dim() == 3:
+    general = variables > 1 or (equations or variables) > 1 or row_weights
+    if c.dim() == 3 and not general:
         N, T, k = c.shape
         steps = T if steps is None else steps
         c2, b2, h2 = c.reshape(N * T, k), b.reshape(N * T), h.reshape(N * T)
     else:
-        k = c.shape[1]
-        N = w.shape[0]
-        if steps is None:
-            raise ValueError("steps is required for the flattened layout")
-        c2, b2, h2 = c, b, h
-    order = k - 1 if order is None else order
-    init_points = u0.shape[1] if u0 is not None and u0.dim() == 3 else 1
+        if steps is None or (general and (order is None or n_init is None)):
+            raise ValueError("steps (and, for several variables or per-row weights, order and n_init) are required")
+        N = len(steps) if not np.isscalar(steps) else (u0.shape[0] if u0 is not None else w.shape[0])
+        c2, b2, h2 = c.reshape(h.numel(), -1), b.reshape(-1), h.reshape(-1)
+    k = c2.shape[1] // max(1, (equations or variables))
+    order = k // variables - 1 if order is None else order
+    if init_points is None:
+        init_points = u0.shape[1] if u0 is not None and u0.dim() == 3 and not general else 1
     if n_init is None:
         n_init = u0.shape[-1] if u0 is not None else 0
     plan = get_plan(order, n_init, N, steps, mode=mode, refine_steps=refine_steps, chunk=chunk,
-                    init_points=init_points)
+                    init_points=init_points, variables=variables, equations=equations, row_weights=row_weights)
     y = SmnnSolve.apply(c2, b2, h2, u0, w, plan)
-    return y.reshape(shape)
+    return y.reshape(shape) if not general else y

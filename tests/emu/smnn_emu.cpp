@@ -19,14 +19,15 @@ namespace {
 
 int g_init_points = 1;   // T_init of the next calls (emu_set_init_points)
 
-template <int K, int L0, int L1, class TIO>
+template <int K, int L0, int L1, class TIO, class F = FormScalar>
 struct Emu {
-  static constexpr int Q = Dim<K>::Q, KK = Dim<K>::KK, REC = Q + KK;
+  static constexpr int Q = Dim<K>::Q, KK = Dim<K>::KK, REC = Q + KK, QE = F::QE, V = F::V;
   int n_init;
   int t_init = 1;
   std::vector<Level> lv;
   std::vector<std::vector<double>> rec, rhs, x;   // per level >= 1
   const TIO *c, *d, *s, *u0, *w;
+  const TIO *wg = nullptr, *wi = nullptr, *wsm = nullptr;   // per-row weights (F::WROW)
 
   Inst<K> inst(int64_t i) const {
     Inst<K> p{};
@@ -37,14 +38,15 @@ struct Emu {
   }
 
   template <int RHS>
-  Src0<K, TIO, RHS> src0(int64_t i, const TIO* g, const TIO* v) const {
-    Src0<K, TIO, RHS> S;
+  Src0<K, TIO, RHS, F> src0(int64_t i, const TIO* g, const TIO* v) const {
+    Src0<K, TIO, RHS, F> S;
     const int64_t o = lv[0].node_off[i];
-    S.c = c + o * K; S.d = d + o; S.s = s + o;
+    S.c = c + o * QE * K; S.d = d + o * QE; S.s = s + o;
+    S.wg = wg ? wg + o * QE : nullptr; S.wsm = wsm ? wsm + o : nullptr; S.wi = wi;
     S.g = g ? g + o * K : nullptr; S.v = v ? v + o * K : nullptr;
     S.n = lv[0].n[i]; S.p = inst(i);
     S.u = u0;
-    S.uo = static_cast<int>(i * t_init * n_init);
+    S.uo = static_cast<int>(i * t_init * V * n_init);
     return S;
   }
 
@@ -133,7 +135,7 @@ struct Emu {
   // level-0 back-substitution that forms the gradients (mirrors OUT_GRAD)
   template <int RHS>
   void backsub0_grad(const TIO* g, const TIO* v, const TIO* y, TIO* dc, TIO* dd, TIO* ds, TIO* du0,
-                     std::vector<double>& dw_part) {
+                     std::vector<double>& dw_part, TIO* dwg = nullptr, TIO* dwi = nullptr, TIO* dws = nullptr) {
     constexpr bool ADD = (RHS == RHS_RESID || RHS == RHS_GRESID);
     const Level& lvl = lv[0];
     dw_part.assign(lvl.chunks * 3, 0.0);
@@ -147,11 +149,14 @@ struct Emu {
       if (G.has_right) for (int e = 0; e < K; ++e) xr[e] = x[1][(up + j) * K + e];
       const auto S = src0<RHS>(i, g, v);
       const int64_t o = lvl.node_off[i];
-      GradSink<K, TIO, ADD> sink;
+      GradSink<K, TIO, ADD, F> sink;
       sink.c = S.c; sink.d = S.d; sink.s = S.s;
+      sink.wg = S.wg; sink.wsm = S.wsm; sink.wi = S.wi;
       sink.y = y + o * K;
       sink.v = v ? v + o * K : nullptr;
-      sink.dc = dc + o * K; sink.dd = dd + o; sink.ds = ds + o; sink.du0 = du0 + i * t_init * n_init;
+      sink.dc = dc + o * QE * K; sink.dd = dd + o * QE; sink.ds = ds + o;
+      sink.du0 = du0 + i * t_init * V * n_init;
+      if (F::WROW) { sink.dwg = dwg + o * QE; sink.dws = dws + o; sink.dwi = dwi + i * t_init * V * n_init; }
       sink.u = S.u;
       sink.uo = S.uo;
       sink.p = S.p;
@@ -159,7 +164,7 @@ struct Emu {
       backsub_chunk<K, L0>(S, G.a, G.b, G.has_left, G.has_right, xl, xr, xs, sink);
       if (G.has_left) sink.left(G.a - 1, xl);
       if (!G.has_right) {
-        sink.ds[lvl.n[i] - 1] = (TIO)0;
+        sink.last_point(lvl.n[i]);
         sink.zero_past_end(lvl.n[i]);
       }
       for (int e = 0; e < 3; ++e) dw_part[ch * 3 + e] = sink.dw[e];
@@ -308,6 +313,87 @@ struct Runner {
   }
 };
 
+// General instance shape (V variables, QE governing equations, per-row
+// weights when F::WROW): forward and backward with the refinement of the
+// refined modes.  w is [N][3] (scalar weights) or unused; wg [S][QE],
+// wi [N][t_init][V][n_init] and ws [S] hold per-row weights.
+template <int K, int L0, int L1, class F>
+struct RunnerG {
+  using E_t = Emu<K, L0, L1, double, F>;
+  static void setup(E_t& E, int n_init, int64_t N, const int64_t* T, const double* c, const double* d,
+                    const double* s, const double* u0, const double* w, const double* wg, const double* wi,
+                    const double* ws) {
+    E.n_init = n_init;
+    E.t_init = g_init_points;
+    E.lv = build_levels(std::vector<int64_t>(T, T + N), L0, L1);
+    E.c = c; E.d = d; E.s = s; E.u0 = u0; E.w = w;
+    E.wg = wg; E.wi = wi; E.wsm = ws;
+    E.alloc();
+  }
+  static int forward(int n_init, int64_t N, const int64_t* T, const double* c, const double* d, const double* s,
+                     const double* u0, const double* w, const double* wg, const double* wi, const double* ws,
+                     double* y, int refine) {
+    E_t E;
+    setup(E, n_init, N, T, c, d, s, u0, w, wg, wi, ws);
+    const int64_t S = E.lv[0].nodes;
+    std::vector<double> b0(S * K), b1(S * K);
+    double* bufs[2] = {b0.data(), b1.data()};
+    double* dst = refine == 0 ? y : bufs[0];
+    E.template solve<RHS_BETA>(true, nullptr, nullptr, dst, nullptr);
+    for (int m = 1; m <= refine; ++m) {
+      double* prev = dst;
+      dst = (m == refine) ? y : bufs[m % 2];
+      E.template solve<RHS_RESID>(false, nullptr, prev, dst, nullptr);
+    }
+    return 0;
+  }
+  static int backward(int n_init, int64_t N, const int64_t* T, const double* c, const double* d, const double* s,
+                      const double* u0, const double* w, const double* wg, const double* wi, const double* ws,
+                      const double* y, const double* gy, double* dc, double* dd, double* ds, double* du0,
+                      double* dw, double* dwg, double* dwi, double* dws, int refine) {
+    E_t E;
+    setup(E, n_init, N, T, c, d, s, u0, w, wg, wi, ws);
+    const int64_t S = E.lv[0].nodes;
+    std::vector<double> b0(S * K), b1(S * K);
+    double* bufs[2] = {b0.data(), b1.data()};
+    std::vector<double> dwp;
+    const int nl = (int)E.lv.size();
+    auto upper = [&](auto rhs_tag, const double* v) {
+      constexpr int RHS = decltype(rhs_tag)::value;
+      for (int l = 0; l + 1 < nl; ++l) {
+        if (l == 0) E.template reduce<RHS>(0, false, gy, v);
+        else E.template reduce<RHS_BETA>(l, false, nullptr, nullptr);
+      }
+      for (int l = nl - 1; l >= 1; --l) E.backsubN(l);
+    };
+    E.template solve<RHS_BETA>(true, nullptr, nullptr, b1.data(), nullptr);
+    const double* prev = nullptr;
+    if (refine > 0) {
+      double* dst = bufs[0];
+      E.template solve<RHS_G>(false, gy, nullptr, dst, nullptr);
+      for (int m = 1; m < refine; ++m) {
+        double* nd = bufs[m % 2];
+        E.template solve<RHS_GRESID>(false, gy, dst, nd, nullptr);
+        dst = nd;
+      }
+      prev = dst;
+      upper(std::integral_constant<int, RHS_GRESID>{}, prev);
+      E.template backsub0_grad<RHS_GRESID>(gy, prev, y, dc, dd, ds, du0, dwp, dwg, dwi, dws);
+    } else {
+      upper(std::integral_constant<int, RHS_G>{}, nullptr);
+      E.template backsub0_grad<RHS_G>(gy, nullptr, y, dc, dd, ds, du0, dwp, dwg, dwi, dws);
+    }
+    if (!F::WROW)
+      for (int64_t i = 0; i < N; ++i) {
+        double acc[3] = {0, 0, 0};
+        for (int64_t ch = E.lv[0].chunk_off[i]; ch < E.lv[0].chunk_off[i + 1]; ++ch)
+          for (int e = 0; e < 3; ++e) acc[e] += dwp[ch * 3 + e];
+        for (int e = 0; e < 3; ++e) dw[i * 3 + e] = acc[e];
+      }
+    return 0;
+  }
+};
+
 }  // namespace
 
 #define DISPATCH(KV, LV, FN, ...)                                                      \
@@ -361,4 +447,36 @@ int emu_backward_f64(int K, int Lc, int Lu, int n_init, int64_t N, const int64_t
   return -1;
 }
 #undef TYPE
+
+#define DISPATCH_G(KV, LV, VV, QV, WV, FN, ...)                                                      \
+  if (K == KV && Lc == LV && Lu == LV && V == VV && QE == QV && wrow == WV)                            \
+    return RunnerG<KV, LV, LV, Form<VV, QV, (WV != 0)>>::FN(__VA_ARGS__);
+
+int emu_forward_gen(int K, int Lc, int Lu, int V, int QE, int wrow, int n_init, int64_t N, const int64_t* T,
+                    const double* c, const double* d, const double* s, const double* u0, const double* w,
+                    const double* wg, const double* wi, const double* ws, double* y, int refine) {
+  DISPATCH_G(2, 4, 1, 1, 1, forward, n_init, N, T, c, d, s, u0, w, wg, wi, ws, y, refine)
+  DISPATCH_G(3, 4, 1, 1, 1, forward, n_init, N, T, c, d, s, u0, w, wg, wi, ws, y, refine)
+  DISPATCH_G(4, 4, 2, 2, 0, forward, n_init, N, T, c, d, s, u0, w, wg, wi, ws, y, refine)
+  DISPATCH_G(4, 4, 2, 2, 1, forward, n_init, N, T, c, d, s, u0, w, wg, wi, ws, y, refine)
+  DISPATCH_G(4, 4, 2, 1, 0, forward, n_init, N, T, c, d, s, u0, w, wg, wi, ws, y, refine)
+  return -1;
+}
+int emu_backward_gen(int K, int Lc, int Lu, int V, int QE, int wrow, int n_init, int64_t N, const int64_t* T,
+                     const double* c, const double* d, const double* s, const double* u0, const double* w,
+                     const double* wg, const double* wi, const double* ws, const double* y, const double* gy,
+                     double* dc, double* dd, double* ds, double* du0, double* dw, double* dwg, double* dwi,
+                     double* dws, int refine) {
+  DISPATCH_G(2, 4, 1, 1, 1, backward, n_init, N, T, c, d, s, u0, w, wg, wi, ws, y, gy, dc, dd, ds, du0, dw, dwg,
+             dwi, dws, refine)
+  DISPATCH_G(3, 4, 1, 1, 1, backward, n_init, N, T, c, d, s, u0, w, wg, wi, ws, y, gy, dc, dd, ds, du0, dw, dwg,
+             dwi, dws, refine)
+  DISPATCH_G(4, 4, 2, 2, 0, backward, n_init, N, T, c, d, s, u0, w, wg, wi, ws, y, gy, dc, dd, ds, du0, dw, dwg,
+             dwi, dws, refine)
+  DISPATCH_G(4, 4, 2, 2, 1, backward, n_init, N, T, c, d, s, u0, w, wg, wi, ws, y, gy, dc, dd, ds, du0, dw, dwg,
+             dwi, dws, refine)
+  DISPATCH_G(4, 4, 2, 1, 0, backward, n_init, N, T, c, d, s, u0, w, wg, wi, ws, y, gy, dc, dd, ds, du0, dw, dwg,
+             dwi, dws, refine)
+  return -1;
+}
 }

@@ -65,6 +65,13 @@ def io_batch(bt, mode):
     return bt.astype(np.float32).astype(np.float64) if mode == "fp32r" else bt
 
 
+def pack_weights(bt):
+    """The per-row weight buffer of the C-ABI: governing [S][Q], initial
+    [N][T_init][V][n_init], smoothness [S]."""
+    wr = bt.wrow
+    return np.concatenate([np.ravel(wr["wg"]), np.ravel(wr["wi"]), np.ravel(wr["ws"])])
+
+
 def run(bt, mode, gy=None, chunk=0, block=0, max_blocks=0, refine_steps=-1, device="cuda:0", info=True,
         chunk_upper=0):
     """Forward (and backward when gy is given) through the C-ABI; numpy results."""
@@ -73,22 +80,37 @@ def run(bt, mode, gy=None, chunk=0, block=0, max_blocks=0, refine_steps=-1, devi
     dev = torch.device(device)
     dt = dtype_for(mode)
     steps = int(bt.T[0]) if np.all(bt.T == bt.T[0]) else bt.T
+    rows = bt.wrow is not None
     p = Plan(bt.R, bt.n_init, bt.n_inst, steps, mode=mode, chunk=chunk, block=block, max_blocks=max_blocks,
-             refine_steps=refine_steps, chunk_upper=chunk_upper, init_points=bt.t_init)
+             refine_steps=refine_steps, chunk_upper=chunk_upper, init_points=bt.t_init, variables=bt.V,
+             equations=bt.Q, row_weights=rows)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
-    c, b, h, u0, w = t(bt.c), t(bt.b), t(bt.h), t(bt.u0.reshape(bt.n_inst, bt.t_init * bt.n_init)), t(bt.w)
+    S, K, Q, N = bt.total_steps, bt.block, bt.Q, bt.n_inst
+    ni = bt.t_init * bt.V * bt.n_init
+    c, b, h, u0 = t(np.reshape(bt.c, (S, Q * K))), t(np.reshape(bt.b, (S * Q,))), t(bt.h), t(np.reshape(bt.u0, (N, ni)))
+    w = t(pack_weights(bt)) if rows else t(bt.w)
     y = torch.empty((p.total_steps, p.k), dtype=dt, device=dev)
     fac, ws = p.new_factor(dev), p.new_workspace(dev)
     inf = torch.full((bt.n_inst,), -7, dtype=torch.int32, device=dev) if info else None
     p.forward(c, b, h, u0, w, y, fac, ws, inf)
     out = {"plan": p}
     if gy is not None:
-        g = t(gy)
+        g = t(np.reshape(gy, (S, K)))
         dc, db, dh = torch.empty_like(c), torch.empty_like(b), torch.empty_like(h)
         du0, dw = torch.empty_like(u0), torch.empty_like(w)
         p.backward(c, b, h, u0, w, y, fac, g, dc, db, dh, du0, dw, ws, None)
-        for key, v in (("dc", dc), ("dd", db), ("ds", dh), ("du0", du0), ("dw", dw)):
-            out[key] = v.double().cpu().numpy()
+        torch.cuda.synchronize(dev)
+        out["dc"] = dc.double().cpu().numpy().reshape(np.shape(bt.c))
+        out["dd"] = db.double().cpu().numpy().reshape(np.shape(bt.b))
+        out["ds"] = dh.double().cpu().numpy()
+        out["du0"] = du0.double().cpu().numpy().reshape(np.shape(bt.u0))
+        dwn = dw.double().cpu().numpy()
+        if rows:
+            out["dwg"] = dwn[:S * Q].reshape(np.shape(bt.wrow["wg"]))
+            out["dwi"] = dwn[S * Q:S * Q + N * ni].reshape(np.shape(bt.wrow["wi"]))
+            out["dws"] = dwn[S * Q + N * ni:]
+        else:
+            out["dw"] = dwn.reshape(N, 3)
     torch.cuda.synchronize(dev)
     out["y"] = y.double().cpu().numpy()
     if info:
@@ -165,6 +187,57 @@ def compare(bt, out, ref, idx, ref_off=None):
     return {k: np.asarray(v, dtype=np.float64) for k, v in m.items()}
 
 
+GRADS_ROW = ("dc", "dd", "ds", "du0", "dwg", "dwi", "dws")
+
+
+def compare_general(bt, out, ref, idx):
+    """compare() for a batch of any instance shape (V variables, Q governing
+    equations, per-row weights): y per variable and order (relative 2-norm and
+    element by element), every gradient in the term-scaled metric (scales
+    from metrics.grad_scales_general) and as raw relative errors, and the
+    backward errors of y.  ref holds oracle arrays for every instance."""
+    o = bt.offsets
+    K = bt.block
+    m = {"y": [], "y_el": [], "y_nw": [], "y_iel": []}
+    keys = GRADS_ROW if bt.wrow is not None else ("dc", "dd", "ds", "du0", "dw")
+    Q, ni = bt.Q, bt.t_init * bt.V * bt.n_init
+    for i in idx:
+        sl = slice(o[i], o[i + 1])
+        m["y"].append(max(metrics.rel_by_order(out["y"][sl], ref["y"][sl], K)))
+        m["y_el"].append(_el(out["y"][sl], ref["y"][sl], K))
+        nw, iel = _raw(out["y"][sl], ref["y"][sl])
+        m["y_nw"].append(nw)
+        m["y_iel"].append(iel)
+        if "dc" not in out:
+            continue
+        sc = metrics.grad_scales_general(*bt.instance_general(i), ref["y"][sl], ref["lam"][sl])
+        T = int(o[i + 1] - o[i])
+        for key in keys:
+            if key in ("dc",):
+                got, want = out[key][sl].reshape(T, Q, K), ref[key][sl].reshape(T, Q, K)
+            elif key in ("dd", "dwg"):
+                got, want = out[key][sl].reshape(T, Q), ref[key][sl].reshape(T, Q)
+            elif key in ("ds", "dws"):
+                got, want = out[key][sl], ref[key][sl]
+            elif key in ("du0", "dwi"):
+                got = out[key].reshape(bt.n_inst, ni)[i]
+                want = ref[key].reshape(bt.n_inst, ni)[i]
+            else:
+                got, want = out[key][i], ref[key][i]
+            if np.size(want) == 0:
+                continue
+            m.setdefault(key, []).append(metrics.grad_error(got, want, sc[key].reshape(np.shape(want))))
+            if key not in ("dw", "dwi", "dwg", "dws"):
+                raw, raw_el = _raw(got, want)
+                m.setdefault(key + "_raw", []).append(raw)
+                m.setdefault(key + "_el", []).append(raw_el)
+    sub = bt.subset(list(idx))
+    rows = np.concatenate([np.arange(o[i], o[i + 1]) for i in idx])
+    m["eta"] = list(banded.backward_error(sub, out["y"][rows]))
+    m["eta_n"] = list(banded.backward_error(sub, out["y"][rows], normwise=True))
+    return {k: np.asarray(v, dtype=np.float64) for k, v in m.items()}
+
+
 def summary(m):
     """One line: worst value of every metric."""
     return " ".join("%s=%.1e" % (k, float(np.max(v))) for k, v in m.items() if np.size(v))
@@ -201,6 +274,6 @@ def check(mode, m, kappa, order, grads=True):
         for key in ykeys:
             assert m[key][j] <= ty, ("P2", key, j, m[key][j], kappa[j])
         if grads:
-            for key in GRADS:
+            for key in GRADS + ("dwg", "dwi", "dws"):
                 if key in m:
                     assert m[key][j] <= tg, ("gradient", key, j, m[key][j], kappa[j])

@@ -79,3 +79,58 @@ def grad_error(got, ref, scale):
     scale = np.asarray(scale, dtype=np.float64).ravel()
     den = np.linalg.norm(scale)
     return float(np.linalg.norm(got - ref) / den) if den > 0 else float(np.abs(got - ref).max())
+
+
+def grad_scales_general(c, d, s, u, wg, wi, ws, y, lam):
+    """grad_scales for an instance of any shape (V variables, Q governing
+    equations, per-row weights): c [T, Q, K], d [T, Q], s [T], u and wi
+    [t_init, V, n_init], wg [T, Q], ws [T], y and lam [T, K].  Returns the
+    scales of dc, dd, ds, du0, the per-row weight gradients dwg, dwi, dws and
+    the three scalar-weight sums dw."""
+    c = np.abs(np.asarray(c, dtype=np.float64))
+    T, Q, K = c.shape
+    u = np.abs(np.asarray(u, dtype=np.float64))
+    t_init, V, n_init = u.shape
+    k = K // V
+    ay = np.abs(np.asarray(y, dtype=np.float64).reshape(T, K))
+    al = np.abs(np.asarray(lam, dtype=np.float64).reshape(T, K))
+    wg = np.abs(np.asarray(wg, dtype=np.float64)).reshape(T, Q)
+    wi = np.abs(np.asarray(wi, dtype=np.float64)).reshape(u.shape)
+    ws = np.abs(np.asarray(ws, dtype=np.float64)).reshape(T)
+    E = np.einsum("tqk,tk->tq", c, ay) + np.abs(np.asarray(d, dtype=np.float64)).reshape(T, Q)
+    Fm = np.einsum("tqk,tk->tq", c, al)
+    out = {"dc": (wg ** 2)[:, :, None] * (E[:, :, None] * al[:, None, :] + Fm[:, :, None] * ay[:, None, :]),
+           "dd": wg ** 2 * Fm, "dwg": 2 * wg * E * Fm}
+    te = min(t_init, T)
+    yu = ay[:te].reshape(te, V, k)[:, :, :n_init]
+    lu = al[:te].reshape(te, V, k)[:, :, :n_init]
+    su = np.zeros(u.shape)
+    sw = np.zeros(u.shape)
+    su[:te] = wi[:te] ** 2 * lu
+    sw[:te] = 2 * wi[:te] * (yu + u[:te]) * lu
+    out["du0"], out["dwi"] = su, sw
+    ss = np.zeros(T)
+    sws = np.zeros(T)
+    if T > 1:
+        st = np.abs(np.asarray(s, dtype=np.float64).reshape(T)[:T - 1])
+        inv = np.array([1.0 / math.factorial(i) for i in range(k)])
+        for v in range(V):
+            yv, lv = ay[:, v * k:(v + 1) * k], al[:, v * k:(v + 1) * k]
+            for r in range(k):
+                for yt, yn, lt, ln in ((yv[:-1], yv[1:], lv[:-1], lv[1:]), (yv[1:], yv[:-1], lv[1:], lv[:-1])):
+                    rho = st ** r * yn[:, r]
+                    mu = st ** r * ln[:, r]
+                    dy = (r * st ** (r - 1) * yn[:, r]) if r > 0 else np.zeros(T - 1)
+                    dl = (r * st ** (r - 1) * ln[:, r]) if r > 0 else np.zeros(T - 1)
+                    for j in range(r, k):
+                        cf = inv[j - r]
+                        rho = rho + st ** j * cf * yt[:, j]
+                        mu = mu + st ** j * cf * lt[:, j]
+                        if j > 0:
+                            dy = dy + j * st ** (j - 1) * cf * yt[:, j]
+                            dl = dl + j * st ** (j - 1) * cf * lt[:, j]
+                    ss[:-1] += ws[:-1] ** 2 * (dl * rho + mu * dy)
+                    sws[:-1] += 2 * ws[:-1] * rho * mu
+    out["ds"], out["dws"] = ss, sws
+    out["dw"] = np.array([out["dwg"].sum(), sw.sum(), sws.sum()])
+    return out

@@ -129,3 +129,58 @@ def test_reduce_with_known_factor_matches_full_reduce(R, L):
     bad = lib.emu_check_reduce_rhs_f64(bt.k, L, L, bt.n_init, ctypes.c_int64(bt.n_inst), T.ctypes.data_as(_IP),
                                        _p(bt.c), _p(bt.b), _p(bt.h), _p(u0), _p(bt.w), _p(v))
     assert bad == 0
+
+
+def emu_run_gen(lib, bt, L, refine, gy):
+    """The CPU emulator on a batch of any instance shape (V variables, Q
+    governing equations, per-row weights)."""
+    T = np.ascontiguousarray(bt.T, dtype=np.int64)
+    S, N, K = bt.total_steps, bt.n_inst, bt.block
+    f = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    c, d, s, u0, w = f(bt.c).reshape(S, -1), f(bt.b), f(bt.h), f(bt.u0), f(bt.w)
+    wr = bt.wrow
+    wg, wi, ws = (f(wr["wg"]), f(wr["wi"]), f(wr["ws"])) if wr is not None else (None, None, None)
+    nul = ctypes.cast(None, _DP)
+    pp = lambda a: _p(a) if a is not None else nul
+    y = np.zeros((S, K))
+    head = [K, L, L, bt.V, bt.Q, int(wr is not None), bt.n_init, ctypes.c_int64(N), T.ctypes.data_as(_IP)]
+    arrs = [pp(x) for x in (c, d, s, u0, w, wg, wi, ws)]
+    assert lib.emu_forward_gen(*head, *arrs, _p(y), refine) == 0
+    out = {"dc": np.zeros_like(c), "dd": np.zeros_like(d), "ds": np.zeros_like(s), "du0": np.zeros_like(u0),
+           "dw": np.zeros_like(w)}
+    for key, a in (("dwg", wg), ("dwi", wi), ("dws", ws)):
+        out[key] = np.zeros_like(a) if a is not None else None
+    g = f(gy).reshape(S, K)
+    assert lib.emu_backward_gen(*head, *arrs, _p(y), _p(g), *(pp(out[k]) for k in ("dc", "dd", "ds", "du0", "dw",
+                                                                                   "dwg", "dwi", "dws")),
+                                refine) == 0
+    out["y"] = y
+    return {k: v for k, v in out.items() if v is not None}
+
+
+GEN_CASES = [  # (R, V, Q, per-row weights, chunk)
+    (1, 1, 1, True, 4), (2, 1, 1, True, 4), (1, 2, 2, False, 4), (1, 2, 2, True, 4), (1, 2, 1, False, 4)]
+
+
+@pytest.mark.parametrize("R,V,Q,per_row,L", GEN_CASES)
+def test_general_forms_match_oracle(R, V, Q, per_row, L):
+    # V coupled variables with Q governing equations, and per-row weights
+    # (App. A.1-A.2): the emulated partition schedule against the __float128
+    # oracle, plain and refined, on ragged lengths around the chunk boundaries
+    from workloads import coupled_batch
+    lib = ctypes.CDLL(_build())
+    # T = 1 with fewer equations than variables has fewer rows than unknowns
+    Ts = [1, 2, 3, 4, 5, 8, 9, 16, 17, 33, 64, 65, 200][0 if Q >= V else 1:]
+    if V == 1:
+        bt = gaussian_batch(len(Ts), Ts, R=R, seed=5 + R, weights=(1.3, 0.8, 1.1), per_row=per_row)
+    else:
+        bt = coupled_batch(len(Ts), Ts, R=R, V=V, Q=Q, seed=11 + Q, weights=(1.3, 0.8, 1.1), per_row=per_row)
+    gy = np.random.default_rng(3).standard_normal((bt.total_steps, bt.block))
+    ref = H.reference(bt, gy)
+    kappa = banded.cond(bt)
+    for refine in (0, 1):
+        out = emu_run_gen(lib, bt, L, refine, gy)
+        m = H.compare_general(bt, out, ref, range(bt.n_inst))
+        print("R=%d V=%d Q=%d rows=%s refine=%d" % (R, V, Q, per_row, refine), H.summary(m),
+              "kappa<=%.1e" % kappa.max())
+        H.check("fp64r" if refine else "fp64", m, kappa, bt.R)

@@ -191,3 +191,40 @@ def test_quad_oracle_reproduces_exact_fixture(case):
     q = banded.grad(bt, gy, quad=True)
     for key in ("y", "lam", "dc", "dd", "ds", "du0", "dw"):
         assert _rel_max(q[key], want[key]) <= 2 ** -52, key
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_quad_oracle_reproduces_exact_general_fixture(case):
+    # tests/golden/exact_general.json: per-row weights and two coupled
+    # variables (App. A.1-A.2), rational oracle rounded to double
+    from tests import fixtures
+    bt, gy, want = fixtures.load_exact_general(case)
+    q = banded.grad(bt, gy, quad=True)
+    for key in want:
+        assert _rel_max(q[key], want[key]) <= 2 ** -52, key
+
+
+@pytest.mark.parametrize("T,R,V,Q", [(3, 1, 1, 1), (6, 2, 2, 2), (4, 1, 3, 2), (2, 3, 2, 1)])
+def test_row_counts_of_eq8_with_variables_and_equations(T, R, V, Q):
+    # Eq. 8 with V variables and Q equations: m = T Q + T_init V (R_init + 1)
+    # + 2 (T - 1) V (R + 1) rows over n = T V (R + 1) unknowns, each kind
+    # touching only its own point(s)
+    rng = np.random.default_rng(T + R + V + Q)
+    k, K = R + 1, V * (R + 1)
+    c = rng.standard_normal((T, Q, K))
+    rows = exact.rows(R, c, rng.standard_normal((T, Q)), 0.01 * (1 + rng.random(T)), rng.standard_normal((1, V, R)),
+                      np.ones((T, Q)), np.ones((1, V, R)), np.ones(T))
+    kinds = [r[3] for r in rows]
+    assert kinds.count("gov") == T * Q
+    assert kinds.count("init") == V * R
+    assert kinds.count("fwd") == kinds.count("bwd") == (T - 1) * V * k
+    assert len(rows) == T * Q + V * R + 2 * (T - 1) * V * k
+    for sig, co, rhs, kind, key in rows:
+        t = key[0]
+        cols = sorted(co)
+        if kind in ("gov", "init"):
+            assert all(t * K <= j < (t + 1) * K for j in cols)
+        else:
+            v = key[1]
+            assert all(j % K // k == v for j in cols)           # one variable only
+            assert all(t * K <= j < (t + 2) * K for j in cols)

@@ -138,10 +138,12 @@ def _ar1(rng, n_series: int, T: int, rho: float) -> np.ndarray:
 
 
 def gaussian_batch(n_inst: int, T, R: int = 2, seed: int = 0, n_init: int | None = None,
-                   weights=(1.0, 1.0, 1.0), h0: float = 0.01, name: str = "", t_init: int = 1) -> Batch:
+                   weights=(1.0, 1.0, 1.0), h0: float = 0.01, name: str = "", t_init: int = 1,
+                   per_row: bool = False) -> Batch:
     """c_{t,r<R} ~ N(0,1), c_{t,R} = 1+|N(0,1)|, b ~ N(0,1), h = h0*(0.5+U[0,1)),
-    u0 ~ N(0,1) at t_init points, constant weights.  ``T`` is an int (uniform)
-    or an array."""
+    u0 ~ N(0,1) at t_init points, constant weights (or, with ``per_row``,
+    per-row weights log-uniform on [0.5, 2], drawn after everything else).
+    ``T`` is an int (uniform) or an array."""
     rng = np.random.default_rng(seed)
     Ts = np.full(n_inst, int(T), dtype=np.int64) if np.isscalar(T) else np.asarray(T, dtype=np.int64)
     S = int(Ts.sum())
@@ -151,7 +153,45 @@ def gaussian_batch(n_inst: int, T, R: int = 2, seed: int = 0, n_init: int | None
     h = h0 * (0.5 + rng.random(S))
     u0 = rng.standard_normal((n_inst, t_init * n_init))
     w = np.tile(np.asarray(weights, dtype=np.float64), (n_inst, 1))
-    return Batch(R=R, n_init=n_init, T=Ts, c=c, b=b, h=h, u0=u0, w=w, name=name, t_init=t_init)
+    wrow = row_weights(rng, Ts, n_inst, 1, 1, n_init, t_init) if per_row else None
+    return Batch(R=R, n_init=n_init, T=Ts, c=c, b=b, h=h, u0=u0, w=w, name=name, t_init=t_init, wrow=wrow)
+
+
+def row_weights(rng, T, n_inst: int, Q: int = 1, V: int = 1, n_init: int = 1, t_init: int = 1,
+                lo: float = 0.5, hi: float = 2.0) -> dict:
+    """Per-row weights (App. A.1's W = diag(w), unsquared) log-uniform on
+    [lo, hi]: wg [S, Q] per governing row, wi [N, t_init * V * n_init] per
+    initial row, ws [S] per step (the smoothness rows of that step)."""
+    S = int(np.sum(T))
+    lu = lambda shape: np.exp(rng.uniform(math.log(lo), math.log(hi), size=shape))
+    return {"wg": lu((S, Q)), "wi": lu((n_inst, t_init * V * n_init)), "ws": lu(S)}
+
+
+def coupled_batch(n_inst: int, T, R: int = 1, V: int = 2, Q: int | None = None, seed: int = 0,
+                  n_init: int | None = None, weights=(1.0, 1.0, 1.0), h0: float = 0.01, t_init: int = 1,
+                  per_row: bool = False, name: str = "") -> Batch:
+    """V coupled variables per instance (Sec. 3.1) with Q governing equations
+    per point (default Q = V): every coefficient c_{t,q,v,r} ~ N(0,1) except
+    the leading one of equation q on variable q, c_{t,q,q,R} = 1+|N(0,1)|
+    (q < V); b ~ N(0,1) [S, Q]; h = h0 (0.5+U[0,1)); u0 ~ N(0,1) for orders
+    < n_init of every variable at t_init points; scalar weights, or per-row
+    weights log-uniform on [0.5, 2] (``per_row``).  c is [S, Q V (R+1)]."""
+    rng = np.random.default_rng(seed)
+    Q = V if Q is None else Q
+    Ts = np.full(n_inst, int(T), dtype=np.int64) if np.isscalar(T) else np.asarray(T, dtype=np.int64)
+    S = int(Ts.sum())
+    k, K = R + 1, V * (R + 1)
+    n_init = R if n_init is None else n_init
+    c = rng.standard_normal((S, Q, K))
+    for q in range(min(Q, V)):
+        c[:, q, q * k + R] = 1.0 + np.abs(rng.standard_normal(S))
+    b = rng.standard_normal((S, Q))
+    h = h0 * (0.5 + rng.random(S))
+    u0 = rng.standard_normal((n_inst, t_init * V * n_init))
+    w = np.tile(np.asarray(weights, dtype=np.float64), (n_inst, 1))
+    wrow = row_weights(rng, Ts, n_inst, Q, V, n_init, t_init) if per_row else None
+    return Batch(R=R, n_init=n_init, T=Ts, c=c.reshape(S, Q * K), b=b if Q > 1 else b.reshape(S), h=h, u0=u0, w=w,
+                 name=name or "coupled", t_init=t_init, V=V, Q=Q, wrow=wrow)
 
 
 def config(name: str, seed: int | None = None, n_inst: int | None = None, T: int | None = None) -> Batch:
