@@ -99,8 +99,12 @@ struct Tracer {
   }
 };
 
-#define SMNN_LAUNCH(TR, KIND, LEVEL, RHS, OUT, CALL)        \
+// Every launch takes its tiles in the direction opposite to the launch
+// before it (Level0Args::rev), so that it starts on the data the previous
+// launch touched last.
+#define SMNN_LAUNCH(TR, A, KIND, LEVEL, RHS, OUT, CALL)     \
   do {                                                      \
+    (A).rev ^= 1;                                           \
     const bool traced_ = (TR).on(KIND, LEVEL, RHS, OUT);    \
     const hipError_t e_ = (CALL);                           \
     if (traced_) (TR).off();                                \
@@ -117,15 +121,15 @@ smnn_status solve_upper(const smnn_plan* p, const Bound& b, int rhs, bool write_
   const int lt = p->top > 0 ? p->top : nl;   // levels >= lt in one launch
   const Tracer tr{p, st};
   if (nl > 1 && !skip_reduce0)
-    SMNN_LAUNCH(tr, SMNN_K_REDUCE0, 0, rhs, 0,
+    SMNN_LAUNCH(tr, a, SMNN_K_REDUCE0, 0, rhs, 0,
                 launch_reduce0(p->K, p->L0, p->form, p->f32, rhs, write_rec, b.lev[0], b.lev[1], a, p->cfg, st));
   for (int l = 1; l + 1 < nl && l < lt; ++l)
-    SMNN_LAUNCH(tr, SMNN_K_REDUCEN, l, rhs, 0,
+    SMNN_LAUNCH(tr, a, SMNN_K_REDUCEN, l, rhs, 0,
                 launch_reduceN(p->K, p->L1, write_rec, l, b.lev[l], b.lev[l + 1], a, p->cfg, st));
   if (lt < nl)
-    SMNN_LAUNCH(tr, SMNN_K_TOP, lt, rhs, 0, launch_top(p->K, p->L1, lt, b.lev[lt], a, p->cfg, st));
+    SMNN_LAUNCH(tr, a, SMNN_K_TOP, lt, rhs, 0, launch_top(p->K, p->L1, lt, b.lev[lt], a, p->cfg, st));
   for (int l = (lt < nl ? lt : nl) - 1; l >= 1; --l)
-    SMNN_LAUNCH(tr, SMNN_K_BACKSUBN, l, rhs, 0,
+    SMNN_LAUNCH(tr, a, SMNN_K_BACKSUBN, l, rhs, 0,
                 launch_backsubN(p->K, p->L1, l, b.lev[l], l + 1 < nl ? &b.lev[l + 1] : nullptr, a, p->cfg, st));
   return SMNN_OK;
 }
@@ -134,7 +138,7 @@ smnn_status backsub0(const smnn_plan* p, const Bound& b, int rhs, int out_mode, 
                      hipStream_t st) {
   const int nl = static_cast<int>(b.lev.size());
   const Tracer tr{p, st};
-  SMNN_LAUNCH(tr, SMNN_K_BACKSUB0, 0, rhs, out_mode,
+  SMNN_LAUNCH(tr, a, SMNN_K_BACKSUB0, 0, rhs, out_mode,
               launch_backsub0(p->K, p->L0, p->form, p->f32, rhs, out_mode, b.lev[0], nl > 1 ? &b.lev[1] : nullptr,
                               a, p->cfg, st));
   return SMNN_OK;
@@ -157,7 +161,7 @@ smnn_status solve_then_reduce(const smnn_plan* p, const Bound& b, int rhs, bool 
   const smnn_status s = solve_upper(p, b, rhs, write_rec, a, st);
   if (s != SMNN_OK) return s;
   const Tracer tr{p, st};
-  SMNN_LAUNCH(tr, SMNN_K_BACKSUB_REDUCE0, 0, rhs, 0,
+  SMNN_LAUNCH(tr, a, SMNN_K_BACKSUB_REDUCE0, 0, rhs, 0,
               launch_backsub_reduce0(p->K, p->L0, p->form, p->f32, rhs, b.lev[0], b.lev[1], a, p->cfg, st));
   return SMNN_OK;
 }
@@ -514,7 +518,7 @@ smnn_status smnn_backward(const smnn_plan* p, const void* c, const void* b, cons
     }
   }
   const Tracer tr{p, st};
-  if (!p->rows) SMNN_LAUNCH(tr, SMNN_K_DW, 0, 0, 0, launch_dw_reduce(p->f32, bd.lev[0], a, st));
+  if (!p->rows) SMNN_LAUNCH(tr, a, SMNN_K_DW, 0, 0, 0, launch_dw_reduce(p->f32, bd.lev[0], a, st));
   SMNN_HIP(launch_info_finalize(a, info, st));
   return SMNN_OK;
 }

@@ -48,6 +48,8 @@ struct Level0Args {
   int t_init = 1;            // points carrying initial values
   int L0 = 8, L1 = 8;        // chunk lengths of level 0 and of levels >= 1
   int64_t N = 0;
+  mutable int rev = 0;       // 1: take the tiles (instances) in decreasing order; the
+                             // host flips it before every launch of a call
   int wpb = 1;               // waves per workgroup of the launch (set by the launcher)
   int64_t nwaves = 0;        // waves in the grid of the launch (set by the launcher)
 };

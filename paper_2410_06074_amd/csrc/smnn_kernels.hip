@@ -62,7 +62,10 @@ constexpr int WAVE = 64;
 // the 8 XCDs (workgroup b runs on XCD b % 8); the wave index gives each
 // XCD a contiguous range of tiles, so that neighbouring tiles, which share
 // boundary rows and write the two halves of some 64-byte runs, meet in the
-// same L2.  The map is a bijection of [0, nwaves).
+// same L2.  The map is a bijection of [0, nwaves).  Launches alternate
+// the direction in which the tiles are taken (Level0Args::rev), so that a
+// kernel starts with the data the previous one touched last, which the
+// device's last-level (memory-side) cache still holds.
 constexpr int XCDS = 8;
 __device__ __forceinline__ int64_t wave_id(const Level0Args& a) {
   const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / WAVE);
@@ -246,7 +249,8 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduce0(LevelDev l0, Le
   const int lane = lane_id();
   const int64_t G = l0.chunks;
   const int64_t tiles = G > 1 ? (G - 2) / (WAVE - 1) + 1 : 1;
-  for (int64_t tile = wave_id(a); tile < tiles; tile += wave_count(a)) {
+  for (int64_t tw = wave_id(a); tw < tiles; tw += wave_count(a)) {
+    const int64_t tile = a.rev ? tiles - 1 - tw : tw;
     const int64_t g0 = tile * (WAVE - 1);
     const int64_t g1 = g0 + WAVE < G ? g0 + WAVE : G;
     // chunk metadata first: its loads then return ahead of the staged tile
@@ -288,7 +292,8 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduceN(LevelDev lv, Le
   const int lane = lane_id();
   const int64_t G = lv.chunks;
   const int64_t tiles = G > 1 ? (G - 2) / (WAVE - 1) + 1 : 1;
-  for (int64_t tile = wave_id(a); tile < tiles; tile += wave_count(a)) {
+  for (int64_t tw = wave_id(a); tw < tiles; tw += wave_count(a)) {
+    const int64_t tile = a.rev ? tiles - 1 - tw : tw;
     const int64_t g = tile * (WAVE - 1) + lane;
     const bool valid = g < G;
     const int64_t gg = valid ? g : G - 1;
@@ -328,7 +333,8 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsubN(LevelDev lv, L
   const int lane = lane_id();
   const int64_t G = lv.chunks;
   const int64_t tiles = (G + WAVE - 1) / WAVE;
-  for (int64_t tile = wave_id(a); tile < tiles; tile += wave_count(a)) {
+  for (int64_t tw = wave_id(a); tw < tiles; tw += wave_count(a)) {
+    const int64_t tile = a.rev ? tiles - 1 - tw : tw;
     const int64_t g = tile * WAVE + lane;
     if (g >= G) continue;
     const int64_t inst = lv.chunk_inst[g];
@@ -386,7 +392,8 @@ __global__ void __launch_bounds__(256, (Backsub0Waves<K, L, OUT>::value)) k_back
   const int lane = lane_id();
   const int64_t G = l0.chunks;
   const int64_t tiles = (G + WAVE - 1) / WAVE;
-  for (int64_t tile = wave_id(a); tile < tiles; tile += wave_count(a)) {
+  for (int64_t tw = wave_id(a); tw < tiles; tw += wave_count(a)) {
+    const int64_t tile = a.rev ? tiles - 1 - tw : tw;
     const int64_t g0 = tile * WAVE;
     const int64_t g1 = g0 + WAVE < G ? g0 + WAVE : G;
     // chunk metadata first: its loads then return ahead of the staged tile
@@ -514,7 +521,8 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDe
   const int lane = lane_id();
   const int64_t G = l0.chunks;
   const int64_t tiles = (G + OWN - 1) / OWN;
-  for (int64_t tile = wave_id(a); tile < tiles; tile += wave_count(a)) {
+  for (int64_t tw = wave_id(a); tw < tiles; tw += wave_count(a)) {
+    const int64_t tile = a.rev ? tiles - 1 - tw : tw;
     const int64_t t0 = tile * OWN;                   // owned chunks [t0, t1)
     const int64_t t1 = t0 + OWN < G ? t0 + OWN : G;
     const int64_t gb = t0 > 0 ? t0 - 1 : 0;          // tile chunks [gb, ge)
@@ -672,7 +680,8 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_top(LevelDev lv, Level0
   extern __shared__ __align__(16) unsigned char smem[];
   double* base = reinterpret_cast<double*>(smem) + (threadIdx.x / WAVE) * (TopCaps<L>::nodes * PER);
   const int lane = lane_id();
-  for (int64_t inst = wave_id(a); inst < a.N; inst += wave_count(a)) {
+  for (int64_t tw = wave_id(a); tw < a.N; tw += wave_count(a)) {
+    const int64_t inst = a.rev ? a.N - 1 - tw : tw;
     const int64_t off = lv.node_off[inst];
     const int64_t n = lv.node_off[inst + 1] - off;
     const int64_t c0 = lv.chunk_off[inst];
