@@ -97,6 +97,17 @@ def sched_bytes_per_step(R, mode, refine):
     return elems * (4 if mode == "fp32r" else 8)
 
 
+def comp_bytes_per_step(R, mode):
+    """Compulsory bytes per solved step of a forward + backward through this
+    ABI (the lower bound): read the inputs c, b, h (k + 2 values), write the
+    paper's per-step factor L_t, P_t (q + k^2) and y (k); then read dl/dy, y,
+    the factor and the inputs once each and write the gradients (k + 2):
+    2q + 2k^2 + 6k + 6 values, 54 for k = 3, in the I/O element size."""
+    k = R + 1
+    q = k * (k + 1) // 2
+    return (2 * q + 2 * k * k + 6 * k + 6) * (4 if mode == "fp32r" else 8)
+
+
 def make_workload(name, n_inst=None, T=None):
     from workloads import config
     return config(name, n_inst=n_inst, T=T)
@@ -113,7 +124,8 @@ def describe(name, bt, mode):
 
 
 # --------------------------------------------------------------- GPU run
-def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0, graph=True, tune=False, block=0):
+def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0, graph=True, tune=False, block=0,
+             max_blocks=0):
     import numpy as np
     import torch
     from paper_2410_06074_amd import Plan
@@ -127,7 +139,6 @@ def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0, graph=
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt)
     c, b, h, u0, w = t(bt.c), t(bt.b), t(bt.h), t(bt.u0), t(bt.w)
     tuned = None
-    max_blocks = 0
     if tune:
         from paper_2410_06074_amd import autotune
         gy0 = torch.ones_like(c)
@@ -207,7 +218,8 @@ def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0, graph=
     err = 0.0
     for j, i in enumerate(sample_idx):
         err = max(err, max(metrics.rel_by_order(yn[o[i]:o[i + 1]], ref[so[j]:so[j + 1]], K)))
-    return {"plan": plan, "ms": ms, "ms_eager": ms_eager, "graph": graph, "tuned": tuned, "ms_traced": ms_traced, "per_kind": per_kind, "step_bytes": step_bytes,
+    kappa = [float("%.3g" % k) for k in banded.cond(sub)]
+    return {"kappa": kappa, "max_blocks": max_blocks, "plan": plan, "ms": ms, "ms_eager": ms_eager, "graph": graph, "tuned": tuned, "ms_traced": ms_traced, "per_kind": per_kind, "step_bytes": step_bytes,
             "err": err, "levels": plan.levels, "chunk": [plan.chunk, plan.chunk_upper], "refine": plan.refine_steps}
 
 
@@ -347,6 +359,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of hipGraph replays")
     ap.add_argument("--autotune", action="store_true", help="pick the launch mapping with smnn_autotune first")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: library default)")
+    ap.add_argument("--max-blocks", type=int, default=0,
+                    help="persistent launches of at most this many workgroups, tiles from a device work queue")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--copy-rate", action="store_true",
@@ -381,7 +395,7 @@ def main():
         log("mode", m)
         results[m] = run_mode(bt, m, args.steps, args.warmup, sample, chunk=args.chunk,
                               chunk_upper=args.chunk_upper, graph=not args.no_graph, tune=args.autotune,
-                              block=args.block)
+                              block=args.block, max_blocks=args.max_blocks)
         r = results[m]
         log("  %.3f ms/step (eager %.3f, traced %.3f), %.3e steps/s, err %.2e, chunk %s, levels %s"
             % (r["ms"], r["ms_eager"], r["ms_traced"], bt.total_steps / (r["ms"] * 1e-3), r["err"], r["chunk"],
@@ -401,11 +415,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.mode == "fp32r" else "f64",
         "data": "synthetic",
-        "config": describe(args.config, bt, args.mode),
+        "config": dict(describe(args.config, bt, args.mode),
+                       **({"persistent_max_blocks": args.max_blocks} if args.max_blocks else {})),
         "err_vs_fp64_oracle": head["err"],
         "roofline": roofline(head),
         "step_hbm_bytes_algorithmic": int(head["step_bytes"]),
         "step_bandwidth_frac": round(head["step_bytes"] / (head["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "comp_bytes_per_step": comp_bytes_per_step(bt.R, args.mode),
+        "comp_frac": round(value * comp_bytes_per_step(bt.R, args.mode) / 1e9 / HBM_PEAK_GBS, 4),
+        "sampled_instances": sample,
+        "sampled_cond_M": head["kappa"],
         "sched_bytes_per_step": sched_bytes_per_step(bt.R, args.mode, head["refine"]),
         "sched_frac": round(value * sched_bytes_per_step(bt.R, args.mode, head["refine"]) / 1e9 / HBM_PEAK_GBS, 4),
         "modes": {m: {"steps_per_s": round(bt.total_steps / (r["ms"] * 1e-3), 1), "ms_per_step": round(r["ms"], 5),

@@ -125,8 +125,9 @@ typedef struct {
   int32_t chunk;          /* nodes per lane at level 0 (time steps; 4, 8 or 16); 0: default for the order and mode */
   int32_t chunk_upper;    /* nodes per lane at the separator levels >= 1; 0: default for the order */
   int32_t block;          /* threads per workgroup (64..256, multiple of 64); 0: 64 */
-  int32_t max_blocks;     /* >0: persistent grid-stride launch with at most this many
-                             workgroups per kernel; 0: one wavefront per tile */
+  int32_t max_blocks;     /* >0: persistent launches of at most this many workgroups per
+                             kernel, whose waves claim tiles from a device work queue
+                             until none is left; 0: one wavefront per tile */
   int32_t init_points;    /* T_init: leading time points with initial values (Eq. 5); 0: 1.
                              N * T_init * V * n_init must not exceed INT32_MAX */
   int32_t variables;      /* V, coupled variables per instance (Sec. 3.1); 0: 1 */

@@ -27,8 +27,9 @@ struct smnn_plan {
   std::vector<LevelDev> lev;     // device views; rec/rhs/x hold byte offsets until bound
   std::vector<size_t> rec_off, rhs_off, x_off;
   size_t factor_bytes = 0, workspace_bytes = 0;
-  size_t buf_off[2] = {0, 0}, dwp_off = 0, info_off = 0;
+  size_t buf_off[2] = {0, 0}, dwp_off = 0, info_off = 0, queue_off = 0;
   void* meta = nullptr;          // device metadata (chunk_inst, chunk_off, node_off of every level)
+  const int32_t* order = nullptr;  // in meta: instances by decreasing T
   // launch tracing (smnn_trace_enable); mutable: recorded during const calls
   mutable std::vector<hipEvent_t> ev;
   mutable std::vector<smnn_trace_record> rec;
@@ -59,7 +60,11 @@ struct Bound {
   void* buf[2];
   double* dwp;
   uint32_t* info;
+  uint32_t* queue;
 };
+
+// Tile counters of the persistent launches of one call (device work queue).
+constexpr int kQueueSlots = 512;
 
 Bound bind(const smnn_plan* p, void* factor, void* workspace) {
   Bound b;
@@ -75,6 +80,7 @@ Bound bind(const smnn_plan* p, void* factor, void* workspace) {
   b.buf[1] = ws + p->buf_off[1];
   b.dwp = reinterpret_cast<double*>(ws + p->dwp_off);
   b.info = reinterpret_cast<uint32_t*>(ws + p->info_off);
+  b.queue = reinterpret_cast<uint32_t*>(ws + p->queue_off);
   return b;
 }
 
@@ -102,9 +108,11 @@ struct Tracer {
 // Every launch takes its tiles in the direction opposite to the launch
 // before it (Level0Args::rev), so that it starts on the data the previous
 // launch touched last.
+// Persistent launches each claim their tiles from a counter of their own.
 #define SMNN_LAUNCH(TR, A, KIND, LEVEL, RHS, OUT, CALL)     \
   do {                                                      \
     (A).rev ^= 1;                                           \
+    (A).queue = (A).queue_next < (A).queue_slots ? (A).queue_base + (A).queue_next++ : nullptr; \
     const bool traced_ = (TR).on(KIND, LEVEL, RHS, OUT);    \
     const hipError_t e_ = (CALL);                           \
     if (traced_) (TR).off();                                \
@@ -318,6 +326,8 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   wb = align_up(wb + sizeof(double) * 3 * lv[0].chunks);
   p->info_off = wb;
   wb = align_up(wb + sizeof(uint32_t) * p->N);
+  p->queue_off = wb;
+  wb = align_up(wb + sizeof(uint32_t) * kQueueSlots);
   p->factor_bytes = std::max<size_t>(fb, kAlign);
   p->workspace_bytes = wb;
 
@@ -331,7 +341,14 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   }
   const size_t cs = mb;   // level-0 chunk_step
   mb = align_up(mb + sizeof(int64_t) * (lv[0].chunks + 1));
+  const size_t od = mb;   // instances by decreasing T
+  mb = align_up(mb + sizeof(int32_t) * p->N);
   std::vector<char> host(mb, 0);
+  {
+    int32_t* ord = reinterpret_cast<int32_t*>(host.data() + od);
+    for (int64_t i = 0; i < p->N; ++i) ord[i] = static_cast<int32_t>(i);
+    std::stable_sort(ord, ord + p->N, [&](int32_t x, int32_t y) { return T[x] > T[y]; });
+  }
   for (size_t l = 0; l < lv.size(); ++l) {
     std::copy(lv[l].chunk_off.begin(), lv[l].chunk_off.end(), reinterpret_cast<int64_t*>(host.data() + co[l]));
     std::copy(lv[l].node_off.begin(), lv[l].node_off.end(), reinterpret_cast<int64_t*>(host.data() + no[l]));
@@ -361,6 +378,7 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
     p->lev[l].nodes = lv[l].nodes;
   }
   p->lev[0].chunk_step = reinterpret_cast<const int64_t*>(m + cs);
+  p->order = reinterpret_cast<const int32_t*>(m + od);
   *out = p;
   return SMNN_OK;
 }
@@ -448,6 +466,12 @@ smnn_status smnn_forward(const smnn_plan* p, const void* c, const void* b, const
   a.L1 = p->L1;
   a.N = p->N;
   a.info = info ? bd.info : nullptr;
+  a.order = p->order;
+  if (p->cfg.max_blocks > 0) {   // persistent launches: a device work queue per launch
+    a.queue_base = bd.queue;
+    a.queue_slots = kQueueSlots;
+    SMNN_HIP(launch_fill_u32(bd.queue, kQueueSlots, 0u, st));
+  }
   SMNN_HIP(launch_info_init(a, st));
   const bool fused = p->refine > 0 && bd.lev.size() > 1;
   a.out = p->refine == 0 ? y : bd.buf[0];
@@ -493,6 +517,12 @@ smnn_status smnn_backward(const smnn_plan* p, const void* c, const void* b, cons
   a.L1 = p->L1;
   a.N = p->N;
   a.info = info ? bd.info : nullptr;
+  a.order = p->order;
+  if (p->cfg.max_blocks > 0) {   // persistent launches: a device work queue per launch
+    a.queue_base = bd.queue;
+    a.queue_slots = kQueueSlots;
+    SMNN_HIP(launch_fill_u32(bd.queue, kQueueSlots, 0u, st));
+  }
   SMNN_HIP(launch_info_init(a, st));
   smnn_status s;
   if (p->refine == 0) {

@@ -48,6 +48,11 @@ struct Level0Args {
   int t_init = 1;            // points carrying initial values
   int L0 = 8, L1 = 8;        // chunk lengths of level 0 and of levels >= 1
   int64_t N = 0;
+  mutable uint32_t* queue = nullptr;  // persistent launches: this launch's tile counter, one of
+  uint32_t* queue_base = nullptr;     //   queue_slots counters zeroed at the start of the call,
+  int queue_slots = 0;                //   handed out in launch order (queue_next)
+  mutable int queue_next = 0;
+  const int32_t* order = nullptr;  // [N] instances by decreasing T (one-wave-per-instance launches)
   mutable int rev = 0;       // 1: take the tiles (instances) in decreasing order; the
                              // host flips it before every launch of a call
   int wpb = 1;               // waves per workgroup of the launch (set by the launcher)
@@ -102,6 +107,7 @@ hipError_t launch_top(int K, int L, int level, const LevelDev& l, const Level0Ar
 size_t top_lds_bytes(int K, int L);   // per wave
 hipError_t launch_dw_reduce(bool f32, const LevelDev& l0, const Level0Args& a, hipStream_t st);
 hipError_t launch_info_init(const Level0Args& a, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t st);
 
 // LDS bytes one wave of a level-0 kernel stages its tile in (0 if (K, L) is
 // not compiled in).  The largest variant of a mode is the gradient pass.

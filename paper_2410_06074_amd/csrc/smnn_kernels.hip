@@ -78,6 +78,24 @@ __device__ __forceinline__ int64_t wave_id(const Level0Args& a) {
 __device__ __forceinline__ int64_t wave_count(const Level0Args& a) { return a.nwaves; }
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 
+// Tile schedule of a launch.  Without a queue the tiles are dealt out
+// statically: wave w takes tiles w, w + waves, ...  Persistent launches
+// (a capped grid) carry a device work queue instead, a counter that every
+// wave increments to claim its next tile until the tiles run out, so waves
+// that finish early take more.  Every lane of a wave calls these at the
+// same point (wave-uniform control flow), lane 0 claims for the wave.
+__device__ __forceinline__ int64_t claim_tile(const Level0Args& a) {
+  int v = 0;
+  if (lane_id() == 0) v = static_cast<int>(atomicAdd(a.queue, 1u));
+  return static_cast<int64_t>(static_cast<uint32_t>(__shfl(v, 0, WAVE)));
+}
+__device__ __forceinline__ int64_t first_tile(const Level0Args& a) {
+  return a.queue ? claim_tile(a) : wave_id(a);
+}
+__device__ __forceinline__ int64_t next_tile(const Level0Args& a, int64_t tw) {
+  return a.queue ? claim_tile(a) : tw + wave_count(a);
+}
+
 // ---------------------------------------------------------- LDS staging
 // Per-step arrays a level-0 kernel variant reads (c and s always; the
 // per-row governing and smoothness weights with per-row weights).
@@ -249,7 +267,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduce0(LevelDev l0, Le
   const int lane = lane_id();
   const int64_t G = l0.chunks;
   const int64_t tiles = G > 1 ? (G - 2) / (WAVE - 1) + 1 : 1;
-  for (int64_t tw = wave_id(a); tw < tiles; tw += wave_count(a)) {
+  for (int64_t tw = first_tile(a); tw < tiles; tw = next_tile(a, tw)) {
     const int64_t tile = a.rev ? tiles - 1 - tw : tw;
     const int64_t g0 = tile * (WAVE - 1);
     const int64_t g1 = g0 + WAVE < G ? g0 + WAVE : G;
@@ -292,7 +310,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduceN(LevelDev lv, Le
   const int lane = lane_id();
   const int64_t G = lv.chunks;
   const int64_t tiles = G > 1 ? (G - 2) / (WAVE - 1) + 1 : 1;
-  for (int64_t tw = wave_id(a); tw < tiles; tw += wave_count(a)) {
+  for (int64_t tw = first_tile(a); tw < tiles; tw = next_tile(a, tw)) {
     const int64_t tile = a.rev ? tiles - 1 - tw : tw;
     const int64_t g = tile * (WAVE - 1) + lane;
     const bool valid = g < G;
@@ -333,10 +351,10 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsubN(LevelDev lv, L
   const int lane = lane_id();
   const int64_t G = lv.chunks;
   const int64_t tiles = (G + WAVE - 1) / WAVE;
-  for (int64_t tw = wave_id(a); tw < tiles; tw += wave_count(a)) {
+  for (int64_t tw = first_tile(a); tw < tiles; tw = next_tile(a, tw)) {
     const int64_t tile = a.rev ? tiles - 1 - tw : tw;
     const int64_t g = tile * WAVE + lane;
-    if (g >= G) continue;
+    if (g < G) {   // (no early continue: the tile schedule is claimed by the whole wave)
     const int64_t inst = lv.chunk_inst[g];
     const int64_t j = g - lv.chunk_off[inst];
     const int64_t off = lv.node_off[inst];
@@ -369,6 +387,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsubN(LevelDev lv, L
 #pragma unroll
       for (int e = 0; e < K; ++e) x[(geo.b + 1) * K + e] = xr[e];
     }
+    }
   }
 }
 
@@ -392,7 +411,7 @@ __global__ void __launch_bounds__(256, (Backsub0Waves<K, L, OUT>::value)) k_back
   const int lane = lane_id();
   const int64_t G = l0.chunks;
   const int64_t tiles = (G + WAVE - 1) / WAVE;
-  for (int64_t tw = wave_id(a); tw < tiles; tw += wave_count(a)) {
+  for (int64_t tw = first_tile(a); tw < tiles; tw = next_tile(a, tw)) {
     const int64_t tile = a.rev ? tiles - 1 - tw : tw;
     const int64_t g0 = tile * WAVE;
     const int64_t g1 = g0 + WAVE < G ? g0 + WAVE : G;
@@ -521,7 +540,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDe
   const int lane = lane_id();
   const int64_t G = l0.chunks;
   const int64_t tiles = (G + OWN - 1) / OWN;
-  for (int64_t tw = wave_id(a); tw < tiles; tw += wave_count(a)) {
+  for (int64_t tw = first_tile(a); tw < tiles; tw = next_tile(a, tw)) {
     const int64_t tile = a.rev ? tiles - 1 - tw : tw;
     const int64_t t0 = tile * OWN;                   // owned chunks [t0, t1)
     const int64_t t1 = t0 + OWN < G ? t0 + OWN : G;
@@ -680,8 +699,9 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_top(LevelDev lv, Level0
   extern __shared__ __align__(16) unsigned char smem[];
   double* base = reinterpret_cast<double*>(smem) + (threadIdx.x / WAVE) * (TopCaps<L>::nodes * PER);
   const int lane = lane_id();
-  for (int64_t tw = wave_id(a); tw < a.N; tw += wave_count(a)) {
-    const int64_t inst = a.rev ? a.N - 1 - tw : tw;
+  for (int64_t tw = first_tile(a); tw < a.N; tw = next_tile(a, tw)) {
+    // instances longest first (the plan's order), so the longest chains start first
+    const int64_t inst = a.order ? a.order[tw] : tw;
     const int64_t off = lv.node_off[inst];
     const int64_t n = lv.node_off[inst + 1] - off;
     const int64_t c0 = lv.chunk_off[inst];

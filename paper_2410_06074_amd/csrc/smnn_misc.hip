@@ -39,6 +39,11 @@ __global__ void k_info_init(uint32_t* info, int64_t N) {
   if (i < N) info[i] = 0xFFFFFFFFu;
 }
 
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t value) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
 __global__ void k_info_finalize(const uint32_t* ws, int32_t* info, int64_t N) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   // 1 + the failing step, saturated at INT32_MAX for steps beyond it
@@ -58,6 +63,14 @@ hipError_t launch_info_init(const Level0Args& a, hipStream_t st) {
   if (!a.info) return hipSuccess;
   const dim3 grid(static_cast<unsigned>((a.N + 255) / 256)), block(256);
   hipLaunchKernelGGL(k_info_init, grid, block, 0, st, a.info, a.N);
+  return hipGetLastError();
+}
+
+// A fill kernel (not a memset node) so that the call stays capturable.
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid(static_cast<unsigned>((n + 255) / 256)), block(256);
+  hipLaunchKernelGGL(k_fill_u32, grid, block, 0, st, p, n, value);
   return hipGetLastError();
 }
 

@@ -100,3 +100,50 @@ def test_autograd_function_matches_abi_and_gradcheck():
     f = lambda *a: solve(*a, mode="fp64r")
     # finite differences of a least-squares solve: relative step 1e-6, loose tolerances
     assert torch.autograd.gradcheck(f, args, eps=1e-6, atol=1e-5, rtol=1e-4)
+
+
+@pytest.mark.parametrize("mode", ["fp32r", "fp64r"])
+def test_ragged_persistent_work_queue_captured(mode):
+    # the ragged order-3 configuration's shape (lengths U{50..5000}, log-uniform
+    # weights), 256 instances: persistent launches whose waves claim tiles from
+    # the device work queue, captured in a hipGraph and replayed with eager
+    # work in between; every replay bitwise equal to the one-wave-per-tile
+    # eager call, which itself matches the oracle on sampled instances
+    import torch
+    from paper_2410_06074_amd import CapturedSolve, Plan
+    dev = torch.device("cuda:0")
+    bt = H.io_batch(config("c3", n_inst=256), mode)
+    gy_np = np.random.default_rng(3).standard_normal(bt.c.shape)
+    if mode == "fp32r":
+        gy_np = gy_np.astype(np.float32).astype(np.float64)
+    ref_out = H.run(bt, mode, gy_np)
+    idx = [0, int(np.argmax(bt.T)), int(np.argmin(bt.T))]
+    sub = bt.subset(idx)
+    o, so = bt.offsets, sub.offsets
+    g_sub = np.concatenate([gy_np[o[i]:o[i + 1]] for i in idx])
+    ref = H.reference(sub, g_sub)
+    rows = np.concatenate([np.arange(o[i], o[i + 1]) for i in idx])
+    got = {"y": ref_out["y"][rows], "dc": ref_out["dc"][rows], "dd": ref_out["dd"][rows],
+           "ds": ref_out["ds"][rows], "du0": ref_out["du0"][idx], "dw": ref_out["dw"][idx]}
+    m = H.compare(sub, got, ref, range(len(idx)))
+    kappa = banded.cond(sub)
+    print("ragged persistent %s" % mode, H.summary(m), "kappa", kappa, flush=True)
+    H.check(mode, m, kappa, bt.R)
+
+    dt = H.dtype_for(mode)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    p = Plan(bt.R, bt.n_init, bt.n_inst, bt.T, mode=mode, block=128, max_blocks=96)
+    ins = [t(bt.c), t(bt.b), t(bt.h), t(bt.u0), t(bt.w)]
+    y = torch.empty((p.total_steps, p.k), dtype=dt, device=dev)
+    fac, ws, gy = p.new_factor(dev), p.new_workspace(dev), t(gy_np)
+    grads = [torch.empty_like(x) for x in ins]
+    cap = CapturedSolve(p, *ins, y, fac, ws, gy=gy, grads=grads)
+    want = [ref_out["y"], ref_out["dc"], ref_out["dd"], ref_out["ds"], ref_out["du0"], ref_out["dw"]]
+    for rep in range(3):
+        for x in [y] + grads:
+            x.zero_()
+        torch.cuda.synchronize()
+        cap.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(want, [y] + grads):
+            assert np.array_equal(a, b.double().cpu().numpy().reshape(a.shape)), rep
