@@ -52,6 +52,10 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     for K, forms in ((4, 2), (3, 0), (4, 0), (2, 0), (5, 0), (2, 1), (3, 1), (4, 1), (5, 1)):
         units.append([hipcc, *COMMON, f"-DSMNN_TU_K={K}", f"-DSMNN_TU_FORMS={forms}", "-c",
                       os.path.join(CSRC, "smnn_kernels.hip"), "-o", os.path.join(BUILD, f"smnn_kernels_k{K}f{forms}.o")])
+    # wide blocks (K = 6, 9): one 16-lane group per chunk
+    for K in (9, 6):
+        units.append([hipcc, *COMMON, f"-DSMNN_TU_K={K}", "-c", os.path.join(CSRC, "smnn_wide.hip"),
+                      "-o", os.path.join(BUILD, f"smnn_wide_k{K}.o")])
     units.append([hipcc, *COMMON, "-c", os.path.join(CSRC, "smnn_misc.hip"), "-o", os.path.join(BUILD, "smnn_misc.o")])
     units.append([hipcc, *COMMON, "-c", os.path.join(CSRC, "smnn_noalloc.hip"),
                   "-o", os.path.join(BUILD, "smnn_noalloc.o")])

@@ -17,6 +17,7 @@ struct smnn_plan {
   int R = 0, K = 0, n_init = 0, mode = 0, refine = 0, L0 = 8, L1 = 8;
   int V = 1, QE = 1;          // variables and governing equations per point (K = V (R+1))
   bool rows = false;          // per-row weights
+  bool wide = false;          // K > 5: one 16-lane group per chunk (smnn_wide.hip)
   int form = 0;               // FormId of the level-0 kernels
   int t_init = 1;   // time points carrying initial values
   int top = 0;      // > 0: levels >= top are solved by one launch per solve (launch_top)
@@ -128,6 +129,18 @@ smnn_status solve_upper(const smnn_plan* p, const Bound& b, int rhs, bool write_
   const int nl = static_cast<int>(b.lev.size());
   const int lt = p->top > 0 ? p->top : nl;   // levels >= lt in one launch
   const Tracer tr{p, st};
+  if (p->wide) {   // every level by its own launches, no one-launch upper levels
+    if (nl > 1)
+      SMNN_LAUNCH(tr, a, SMNN_K_REDUCE0, 0, rhs, 0,
+                  launch_wreduce0(p->K, p->L0, p->form, p->f32, rhs, write_rec, b.lev[0], b.lev[1], a, p->cfg, st));
+    for (int l = 1; l + 1 < nl; ++l)
+      SMNN_LAUNCH(tr, a, SMNN_K_REDUCEN, l, rhs, 0,
+                  launch_wreduceN(p->K, p->L1, write_rec, l, b.lev[l], b.lev[l + 1], a, p->cfg, st));
+    for (int l = nl - 1; l >= 1; --l)
+      SMNN_LAUNCH(tr, a, SMNN_K_BACKSUBN, l, rhs, 0,
+                  launch_wbacksubN(p->K, p->L1, l, b.lev[l], l + 1 < nl ? &b.lev[l + 1] : nullptr, a, p->cfg, st));
+    return SMNN_OK;
+  }
   if (nl > 1 && !skip_reduce0)
     SMNN_LAUNCH(tr, a, SMNN_K_REDUCE0, 0, rhs, 0,
                 launch_reduce0(p->K, p->L0, p->form, p->f32, rhs, write_rec, b.lev[0], b.lev[1], a, p->cfg, st));
@@ -146,6 +159,12 @@ smnn_status backsub0(const smnn_plan* p, const Bound& b, int rhs, int out_mode, 
                      hipStream_t st) {
   const int nl = static_cast<int>(b.lev.size());
   const Tracer tr{p, st};
+  if (p->wide) {
+    SMNN_LAUNCH(tr, a, SMNN_K_BACKSUB0, 0, rhs, out_mode,
+                launch_wbacksub0(p->K, p->L0, p->form, p->f32, rhs, out_mode, b.lev[0], nl > 1 ? &b.lev[1] : nullptr,
+                                 a, p->cfg, st));
+    return SMNN_OK;
+  }
   SMNN_LAUNCH(tr, a, SMNN_K_BACKSUB0, 0, rhs, out_mode,
               launch_backsub0(p->K, p->L0, p->form, p->f32, rhs, out_mode, b.lev[0], nl > 1 ? &b.lev[1] : nullptr,
                               a, p->cfg, st));
@@ -179,6 +198,7 @@ smnn_status solve_then_reduce(const smnn_plan* p, const Bound& b, int rhs, bool 
 // smoothness weights [S].
 void bind_row_weights(const smnn_plan* p, const void* w, void* dw, Level0Args& a) {
   if (!p->rows) return;
+  a.w = nullptr;   // no scalar weights
   const size_t io = p->f32 ? sizeof(float) : sizeof(double);
   const size_t ng = static_cast<size_t>(p->S) * p->QE;
   const size_t ni = static_cast<size_t>(p->N) * p->t_init * p->V * p->n_init;
@@ -223,12 +243,15 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   if (V > 5 || QE > 5) return SMNN_ERR_UNSUPPORTED;
   const int K = V * (d->order + 1);
   const int form = form_id(V, QE, d->row_weights != 0);
-  if (form < 0 || K > 5) return SMNN_ERR_UNSUPPORTED;
+  const bool wide = K > 5;
+  if (form < 0) return SMNN_ERR_UNSUPPORTED;
   const bool f32 = d->mode == SMNN_MODE_FP32_REFINED;
-  const int L0 = d->chunk ? d->chunk : default_chunk(K, false, f32);
-  const int L1 = d->chunk_upper ? d->chunk_upper : default_chunk(K, true, f32);
+  const int L0 = d->chunk ? d->chunk : (wide ? 4 : default_chunk(K, false, f32));
+  const int L1 = d->chunk_upper ? d->chunk_upper : (wide ? 4 : default_chunk(K, true, f32));
   if (d->chunk < 0 || d->chunk_upper < 0) return SMNN_ERR_INVALID_ARG;
-  if (!supported0(K, L0, form) || !supported(K, L1)) return SMNN_ERR_UNSUPPORTED;
+  if (wide ? !(wide_supported(K, L0, form) && wide_supported(K, L1, form))
+           : !(supported0(K, L0, form) && supported(K, L1)))
+    return SMNN_ERR_UNSUPPORTED;
   std::vector<int64_t> T(static_cast<size_t>(d->n_inst));
   for (int64_t i = 0; i < d->n_inst; ++i) {
     T[i] = d->steps ? d->steps[i] : d->steps_uniform;
@@ -242,6 +265,7 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   p->V = V;
   p->QE = QE;
   p->rows = d->row_weights != 0;
+  p->wide = wide;
   p->form = form;
   p->n_init = d->n_init;
   p->t_init = d->init_points > 0 ? d->init_points : 1;
@@ -271,7 +295,7 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
     const int combos[6][2] = {{RHS_BETA, OUT_STORE}, {RHS_RESID, OUT_STORE}, {RHS_G, OUT_STORE},
                               {RHS_GRESID, OUT_STORE}, {RHS_G, OUT_GRAD}, {RHS_GRESID, OUT_GRAD}};
     for (const auto& cb : combos)
-      if (level0_lds_bytes(K, L0, form, p->f32, cb[0], cb[1]) > static_cast<size_t>(lds_max)) {
+      if (!wide && level0_lds_bytes(K, L0, form, p->f32, cb[0], cb[1]) > static_cast<size_t>(lds_max)) {
         delete p;
         return SMNN_ERR_UNSUPPORTED;
       }
@@ -293,14 +317,20 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
       if (gmax <= 64 && lv[l].nodes <= (int64_t(1) << 19)) p->top = static_cast<int>(l);
     }
   }
-  const int Q = K * (K + 1) / 2, REC = Q + K * K;
+  const int Q = K * (K + 1) / 2;
+  // separator records: packed A and the coupling block; wide blocks keep
+  // full K x K halves of A and the coupling block (3 K^2), and two halves of
+  // the right-hand side
+  const int REC = wide ? 3 * K * K : Q + K * K, RHSW = wide ? 2 * K : K;
   const size_t io = p->f32 ? sizeof(float) : sizeof(double);
 
   // factor: level >= 1 node records
   size_t fb = 0;
   p->rec_off.assign(lv.size(), 0);
-  // separator levels use the interleaved layout: TILE_W chunks x L1 slots per group
+  // separator levels use the interleaved layout: TILE_W chunks x L1 slots
+  // per group (wide blocks: the natural layout, one slot per node)
   auto slots = [&](size_t l) {
+    if (wide) return static_cast<size_t>(lv[l].nodes);
     return static_cast<size_t>((lv[l].chunks + TILE_W - 1) / TILE_W) * TILE_W * L1;
   };
   for (size_t l = 1; l < lv.size(); ++l) {
@@ -313,7 +343,7 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   p->x_off.assign(lv.size(), 0);
   for (size_t l = 1; l < lv.size(); ++l) {
     p->rhs_off[l] = wb;
-    wb = align_up(wb + sizeof(double) * K * slots(l));
+    wb = align_up(wb + sizeof(double) * RHSW * slots(l));
     p->x_off[l] = wb;
     wb = align_up(wb + sizeof(double) * K * lv[l].nodes);
   }
@@ -473,7 +503,7 @@ smnn_status smnn_forward(const smnn_plan* p, const void* c, const void* b, const
     SMNN_HIP(launch_fill_u32(bd.queue, kQueueSlots, 0u, st));
   }
   SMNN_HIP(launch_info_init(a, st));
-  const bool fused = p->refine > 0 && bd.lev.size() > 1;
+  const bool fused = !p->wide && p->refine > 0 && bd.lev.size() > 1;
   a.out = p->refine == 0 ? y : bd.buf[0];
   smnn_status s = fused ? solve_then_reduce(p, bd, RHS_BETA, true, a, st)
                         : solve(p, bd, RHS_BETA, true, OUT_STORE, a, st);
@@ -529,7 +559,7 @@ smnn_status smnn_backward(const smnn_plan* p, const void* c, const void* b, cons
     s = solve(p, bd, RHS_G, false, OUT_GRAD, a, st);
     if (s != SMNN_OK) return s;
   } else {
-    const bool fused = bd.lev.size() > 1;
+    const bool fused = !p->wide && bd.lev.size() > 1;
     a.out = bd.buf[0];
     s = fused ? solve_then_reduce(p, bd, RHS_G, false, a, st)
               : solve(p, bd, RHS_G, false, OUT_STORE, a, st);

@@ -74,15 +74,31 @@ enum FormId : int {
   SMNN_FORM_ROWS = 1,       // V = QE = 1, per-row weights
   SMNN_FORM_V2 = 2,         // V = QE = 2, scalar weights
   SMNN_FORM_V2_ROWS = 3,    // V = QE = 2, per-row weights
-  SMNN_FORM_V2_Q1 = 4       // V = 2, QE = 1, scalar weights
+  SMNN_FORM_V2_Q1 = 4,      // V = 2, QE = 1, scalar weights
+  SMNN_FORM_V3 = 5,         // V = QE = 3, scalar weights
+  SMNN_FORM_V3_ROWS = 6     // V = QE = 3, per-row weights
 };
 // Form id of (V, QE, per-row weights), -1 if none is built.
 inline int form_id(int V, int QE, bool rows) {
   if (V == 1 && QE == 1) return rows ? SMNN_FORM_ROWS : SMNN_FORM_SCALAR;
   if (V == 2 && QE == 2) return rows ? SMNN_FORM_V2_ROWS : SMNN_FORM_V2;
   if (V == 2 && QE == 1 && !rows) return SMNN_FORM_V2_Q1;
+  if (V == 3 && QE == 3) return rows ? SMNN_FORM_V3_ROWS : SMNN_FORM_V3;
   return -1;
 }
+
+// Wide blocks (K > 5, smnn_wide.hip): one 16-lane group per chunk; separator
+// records are full K x K blocks in the natural layout (WRec in smnn_wide.h:
+// 3 K^2 doubles per node; right-hand sides 2 K).
+bool wide_supported(int K, int L, int form);
+hipError_t launch_wreduce0(int K, int L, int form, bool f32, int rhs_mode, bool write_rec, const LevelDev& l0,
+                           const LevelDev& l1, const Level0Args& a, const Launch& cfg, hipStream_t st);
+hipError_t launch_wbacksub0(int K, int L, int form, bool f32, int rhs_mode, int out_mode, const LevelDev& l0,
+                            const LevelDev* l1, const Level0Args& a, const Launch& cfg, hipStream_t st);
+hipError_t launch_wreduceN(int K, int L, bool write_rec, int level, const LevelDev& l, const LevelDev& lnext,
+                           const Level0Args& a, const Launch& cfg, hipStream_t st);
+hipError_t launch_wbacksubN(int K, int L, int level, const LevelDev& l, const LevelDev* lnext,
+                            const Level0Args& a, const Launch& cfg, hipStream_t st);
 
 // All return hipSuccess or the launch error.  K = V (R+1), L = chunk length,
 // form = FormId of the level-0 kernels, f32 selects the float I/O form.
@@ -119,6 +135,9 @@ bool supported0(int K, int L, int form);  // level-0 kernels of the form
 
 // Name of a per-block-size launcher (smnn_kernels.hip is built once per K
 // and group of instance forms).
+#define SMNN_WFN_CAT2(a, b) a##_w##b
+#define SMNN_WFN_CAT(a, b) SMNN_WFN_CAT2(a, b)
+#define SMNN_WFN(name) SMNN_WFN_CAT(name, SMNN_TU_K)
 #ifndef SMNN_TU_FORMS
 #define SMNN_TU_FORMS 0
 #endif

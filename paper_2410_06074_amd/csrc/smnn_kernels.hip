@@ -200,11 +200,11 @@ __device__ __forceinline__ void unstage_rows(void* dst, int w, int64_t r0, int64
 
 template <int K, class TIO>
 __device__ __forceinline__ Inst<K> load_inst(const Level0Args& a, int64_t i) {
-  const TIO* w = static_cast<const TIO*>(a.w);
+  const TIO* w = static_cast<const TIO*>(a.w);   // null with per-row weights
   Inst<K> p;
-  p.wg = static_cast<double>(w[3 * i]);
-  p.wi = static_cast<double>(w[3 * i + 1]);
-  p.ws = static_cast<double>(w[3 * i + 2]);
+  p.wg = w ? static_cast<double>(w[3 * i]) : 0.0;
+  p.wi = w ? static_cast<double>(w[3 * i + 1]) : 0.0;
+  p.ws = w ? static_cast<double>(w[3 * i + 2]) : 0.0;
   p.n_init = a.n_init;
   p.t_init = a.t_init;
   return p;

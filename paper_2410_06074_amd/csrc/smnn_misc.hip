@@ -134,6 +134,56 @@ SMNN_DECL0(k4f2)
     return FN##_k4f2(__VA_ARGS__);                                     \
   }
 
+// wide blocks (smnn_wide.hip, one translation unit per K)
+#define SMNN_DECLW(KV)                                                                                      \
+  bool wide_supported_w##KV(int, int, int);                                                                 \
+  hipError_t launch_wreduce0_w##KV(int, int, int, bool, int, bool, const LevelDev&, const LevelDev&,         \
+                                   const Level0Args&, const Launch&, hipStream_t);                           \
+  hipError_t launch_wbacksub0_w##KV(int, int, int, bool, int, int, const LevelDev&, const LevelDev*,         \
+                                    const Level0Args&, const Launch&, hipStream_t);                          \
+  hipError_t launch_wreduceN_w##KV(int, int, bool, int, const LevelDev&, const LevelDev&, const Level0Args&, \
+                                   const Launch&, hipStream_t);                                              \
+  hipError_t launch_wbacksubN_w##KV(int, int, int, const LevelDev&, const LevelDev*, const Level0Args&,      \
+                                    const Launch&, hipStream_t);
+SMNN_DECLW(6)
+SMNN_DECLW(9)
+#undef SMNN_DECLW
+
+#define SMNN_SWITCHW(FN, ...)                    \
+  switch (K) {                                   \
+    case 6: return FN##_w6(__VA_ARGS__);         \
+    case 9: return FN##_w9(__VA_ARGS__);         \
+  }
+
+bool wide_supported(int K, int L, int form) {
+  SMNN_SWITCHW(wide_supported, K, L, form)
+  return false;
+}
+
+hipError_t launch_wreduce0(int K, int L, int form, bool f32, int rhs_mode, bool write_rec, const LevelDev& l0,
+                           const LevelDev& l1, const Level0Args& a, const Launch& cfg, hipStream_t st) {
+  SMNN_SWITCHW(launch_wreduce0, K, L, form, f32, rhs_mode, write_rec, l0, l1, a, cfg, st)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_wbacksub0(int K, int L, int form, bool f32, int rhs_mode, int out_mode, const LevelDev& l0,
+                            const LevelDev* l1, const Level0Args& a, const Launch& cfg, hipStream_t st) {
+  SMNN_SWITCHW(launch_wbacksub0, K, L, form, f32, rhs_mode, out_mode, l0, l1, a, cfg, st)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_wreduceN(int K, int L, bool write_rec, int level, const LevelDev& l, const LevelDev& lnext,
+                           const Level0Args& a, const Launch& cfg, hipStream_t st) {
+  SMNN_SWITCHW(launch_wreduceN, K, L, write_rec, level, l, lnext, a, cfg, st)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_wbacksubN(int K, int L, int level, const LevelDev& l, const LevelDev* lnext,
+                            const Level0Args& a, const Launch& cfg, hipStream_t st) {
+  SMNN_SWITCHW(launch_wbacksubN, K, L, level, l, lnext, a, cfg, st)
+  return hipErrorInvalidValue;
+}
+
 bool supported(int K, int L) {
   SMNN_SWITCH(supported, K, L)
   return false;

@@ -180,3 +180,64 @@ def test_autograd_function_with_coupled_variables_and_row_weights():
     # the last step slot of each instance enters no row; keep h's perturbation
     # on the others by checking every input (its gradient there is 0)
     assert torch.autograd.gradcheck(f, (c, b, h, u0, w), eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+# ------------------------------------------------ wide blocks (K = V(R+1) > 5)
+# one 16-lane group per chunk, a row of every block per lane
+WIDE = [(2, 2, 2, False), (1, 3, 3, False), (2, 3, 3, False), (2, 3, 3, True)]   # (R, V, Q, per-row weights)
+
+
+@pytest.mark.parametrize("R,V,Q,rows", WIDE)
+@pytest.mark.parametrize("mode", H.MODES)
+def test_wide_blocks_ragged(R, V, Q, rows, mode):
+    bt = H.io_batch(coupled_batch(len(EDGE_T), EDGE_T, R=R, V=V, Q=Q, seed=300 + 10 * V + R, weights=(1.3, 0.8, 1.1),
+                                  per_row=rows, h0=0.05), mode)
+    gy = np.random.default_rng(R + V).standard_normal((bt.total_steps, bt.block))
+    if mode == "fp32r":
+        gy = gy.astype(np.float32).astype(np.float64)
+    ref = H.reference(bt, gy)
+    out = H.run(bt, mode, gy)
+    assert out["plan"].chunk == 4
+    m = H.compare_general(bt, out, ref, range(bt.n_inst))
+    kappa = banded.cond(bt)
+    _print("wide R=%d V=%d Q=%d rows=%s %s" % (R, V, Q, rows, mode), H.summary(m), "kappa<=%.1e" % kappa.max())
+    H.check(mode, m, kappa, bt.R)
+    assert (out["info"] == 0).all()
+
+
+def test_wide_polynomial_trajectory_recovered_at_long_T():
+    # three coupled order-2 variables (9 x 9 blocks), consistent constraints
+    bt, exact = _coupled_polynomial(3, 5000, 2, 3, 3, seed=17)
+    out = H.run(bt, "fp64r")
+    err = H.metrics.rel_by_order(out["y"], exact, bt.block)
+    _print("wide poly", ["%.1e" % e for e in err])
+    assert max(err) < 1e-7 and max(err[0::3]) < 1e-9
+
+
+@pytest.mark.parametrize("mode", ["fp64r", "fp32r"])
+def test_wide_lorenz_shaped_batch_sampled(mode):
+    # 512 instances of three coupled order-2 variables (the Lorenz batch of
+    # Sec. 5.1 as one coupled system per window), T = 1000
+    bt = H.io_batch(coupled_batch(512, 1000, R=2, V=3, Q=3, seed=31), mode)
+    idx = [0, 511]
+    sub = bt.subset(idx)
+    y_ref = banded.solve(sub, quad=True)
+    g_sub = np.zeros_like(y_ref)
+    g_sub[:, 0::3] = 2.0 * y_ref[:, 0::3]
+    ref = banded.grad(sub, g_sub, quad=True)
+    gy = np.zeros((bt.total_steps, bt.block))
+    o, so = bt.offsets, sub.offsets
+    for j, i in enumerate(idx):
+        gy[o[i]:o[i + 1]] = g_sub[so[j]:so[j + 1]]
+    out = H.run(bt, mode, gy)
+    rows_ = np.concatenate([np.arange(o[i], o[i + 1]) for i in idx])
+    got = {"y": out["y"][rows_], "dc": out["dc"][rows_], "dd": out["dd"][rows_], "ds": out["ds"][rows_],
+           "du0": out["du0"][idx], "dw": out["dw"][idx]}
+    m = H.compare_general(sub, got, ref, range(len(idx)))
+    kappa = banded.cond(sub)
+    eta = banded.backward_error(bt.subset(range(0, 512, 16)), out["y"][np.concatenate(
+        [np.arange(o[i], o[i + 1]) for i in range(0, 512, 16)])], normwise=True)
+    _print("wide 512x1000 V=3 R=2 %s" % mode, H.summary(m), "kappa", kappa, "| eta_n max %.1e" % eta.max())
+    H.check(mode, m, kappa, bt.R)
+    assert eta.max() <= 50 * H.U_WORK[mode]
+    assert (out["info"] == 0).all()
