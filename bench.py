@@ -46,34 +46,48 @@ def log(*a):
 # ------------------------------------------------------------ byte model
 def kernel_bytes(rec, plan, io):
     """Algorithmic HBM bytes of one traced launch: every array the launch must
-    read once plus every array it must write once (metadata excluded)."""
+    read once plus every array it must write once (metadata excluded).
+    K = unknowns per point (V (R+1)), QE governing equations per point, per-row
+    weights add QE + 1 values per step to the reads (and to the gradient's
+    writes); separator records are a packed diagonal block and a coupling
+    block (wide blocks: two full halves of the diagonal block and the coupling
+    block, with two halves of the right-hand side)."""
     kind, level, rhs, out = rec[0], rec[1], rec[2], rec[3]
     K = plan.k
+    QE = getattr(plan, "equations", 1)
+    rows = getattr(plan, "row_weights", False)
+    wide = K > 5
     Q = K * (K + 1) // 2
-    REC = Q + K * K
+    REC = 3 * K * K if wide else Q + K * K
+    RHSW = 2 * K if wide else K
     lv = plan.levels                       # [(nodes, chunks)] per level
     S, G0 = lv[0]
     N = plan.n_inst
     n = lambda l: lv[l][0] if l < len(lv) else 0
-    per_inst = N * (plan.n_init + 3) * io
+    n_initial = N * getattr(plan, "n_initial", plan.n_init)
+    per_inst = (N * (0 if rows else 3) + n_initial * (2 if rows else 1)) * io
+    wts = (QE + 1) if rows else 0          # per-row weights read per step
+    base = QE * K + 1 + wts                # c, s (and weights) per step
+    d_el = QE
     if kind == "reduce0":
-        el = K + 1 + (1 if rhs in (RHS_BETA, RHS_RESID) else 0) + (K if rhs in (RHS_G, RHS_GRESID) else 0) \
+        el = base + (d_el if rhs in (RHS_BETA, RHS_RESID) else 0) + (K if rhs in (RHS_G, RHS_GRESID) else 0) \
             + (K if rhs in (RHS_RESID, RHS_GRESID) else 0)
-        w = n(1) * K * 8 + (n(1) * REC * 8 if rhs == RHS_BETA else 0)
+        w = n(1) * RHSW * 8 + (n(1) * REC * 8 if rhs == RHS_BETA else 0)
         return S * el * io + per_inst + w
     if kind == "reduceN":
-        w = n(level + 1) * K * 8 + (n(level + 1) * REC * 8 if rhs == RHS_BETA else 0)
-        return n(level) * (REC + K) * 8 + w
+        w = n(level + 1) * RHSW * 8 + (n(level + 1) * REC * 8 if rhs == RHS_BETA else 0)
+        return n(level) * (REC + RHSW) * 8 + w
     if kind == "backsubN":
-        return n(level) * (REC + K) * 8 + n(level + 1) * K * 8 + n(level) * K * 8
+        return n(level) * (REC + RHSW) * 8 + n(level + 1) * K * 8 + n(level) * K * 8
     if kind == "backsub0":
         grad = out == 1
-        el = K + 1 + (1 if (rhs in (RHS_BETA, RHS_RESID) or grad) else 0) + (K if rhs in (RHS_G, RHS_GRESID) else 0) \
+        el = base + (d_el if (rhs in (RHS_BETA, RHS_RESID) or grad) else 0) + (K if rhs in (RHS_G, RHS_GRESID) else 0) \
             + (K if rhs in (RHS_RESID, RHS_GRESID) else 0) + (K if grad else 0)
-        wr = (K + 2) * S * io + G0 * 3 * 8 + N * plan.n_init * io if grad else K * S * io
+        wr = ((QE * K + QE + 1 + wts) * S * io + (0 if rows else G0 * 3 * 8) + n_initial * (2 if rows else 1) * io
+              if grad else K * S * io)
         return S * el * io + per_inst + n(1) * K * 8 + wr
     if kind == "backsub_reduce0":          # rhs = the solve's form (beta or dl/dy)
-        el = K + 1 + (1 if rhs == RHS_BETA else 0) + (K if rhs == RHS_G else 0)
+        el = base + (d_el if rhs == RHS_BETA else 0) + (K if rhs == RHS_G else 0)
         return S * el * io + per_inst + n(1) * K * 8 + K * S * io + n(1) * K * 8
     if kind == "top":                      # levels >= level: its records and rhs in, its x out
         return n(level) * (REC + K) * 8 + n(level) * K * 8
@@ -97,15 +111,19 @@ def sched_bytes_per_step(R, mode, refine):
     return elems * (4 if mode == "fp32r" else 8)
 
 
-def comp_bytes_per_step(R, mode):
+def comp_bytes_per_step(bt, mode):
     """Compulsory bytes per solved step of a forward + backward through this
-    ABI (the lower bound): read the inputs c, b, h (k + 2 values), write the
-    paper's per-step factor L_t, P_t (q + k^2) and y (k); then read dl/dy, y,
-    the factor and the inputs once each and write the gradients (k + 2):
-    2q + 2k^2 + 6k + 6 values, 54 for k = 3, in the I/O element size."""
-    k = R + 1
-    q = k * (k + 1) // 2
-    return (2 * q + 2 * k * k + 6 * k + 6) * (4 if mode == "fp32r" else 8)
+    ABI (the lower bound): read the inputs c, b, h (Q K + Q + 1 values with K
+    = V (R+1) unknowns per point; k + 2 for one variable), write the paper's
+    per-step factor L_t, P_t (q + K^2, q = K (K+1) / 2) and y (K); then read
+    dl/dy, y, the factor and the inputs once each and write the gradients (as
+    many as the inputs): 3 (Q K + Q + 1) + 2 (q + K^2) + 3 K values, 54 for
+    one order-2 variable, in the I/O element size (per-row weights add Q + 1
+    inputs and as many gradients)."""
+    K, Q = bt.block, bt.Q
+    q = K * (K + 1) // 2
+    inputs = Q * K + Q + 1 + ((Q + 1) if bt.wrow is not None else 0)
+    return (3 * inputs + 2 * (q + K * K) + 3 * K) * (4 if mode == "fp32r" else 8)
 
 
 def make_workload(name, n_inst=None, T=None):
@@ -113,12 +131,23 @@ def make_workload(name, n_inst=None, T=None):
     return config(name, n_inst=n_inst, T=T)
 
 
+def pack_weights(bt):
+    """The per-row weight buffer of the C-ABI (governing, initial, smoothness)."""
+    import numpy as np
+    wr = bt.wrow
+    return np.concatenate([np.ravel(wr["wg"]), np.ravel(wr["wi"]), np.ravel(wr["ws"])])
+
+
 def describe(name, bt, mode):
-    sizes = {"h": "512x3", "c1": "512x3", "c2": "256x128", "c3": "2048", "c4": "4x8", "c0": "1"}
+    sizes = {"h": "512x3", "c1": "512x3", "c2": "256x128", "c3": "2048", "c4": "4x8", "c0": "1", "hw": "512x3",
+             "v2": "1536", "v3": "512"}
     T = int(bt.T[0]) if (bt.T == bt.T[0]).all() else "ragged %d..%d" % (bt.T.min(), bt.T.max())
-    return {"workload": "%s: %s = %d instances, T=%s, R=%d, forward+adjoint, mode %s"
-                        % (name, sizes.get(name, "?"), bt.n_inst, T, bt.R, mode),
+    shape = "" if bt.V == 1 and bt.Q == 1 and bt.wrow is None else ", V=%d, Q=%d%s" % (
+        bt.V, bt.Q, ", per-row weights" if bt.wrow is not None else "")
+    return {"workload": "%s: %s = %d instances, T=%s, R=%d%s, forward+adjoint, mode %s"
+                        % (name, sizes.get(name, "?"), bt.n_inst, T, bt.R, shape, mode),
             "instances": int(bt.n_inst), "steps_per_instance": T, "order_R": int(bt.R),
+            "variables": int(bt.V), "equations": int(bt.Q), "per_row_weights": bt.wrow is not None,
             "total_steps": int(bt.total_steps), "mode": mode,
             "inputs": "seeded synthetic (workloads.config('%s'))" % name}
 
@@ -137,7 +166,11 @@ def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0, graph=
     io = 4 if mode == "fp32r" else 8
     steps_arg = int(bt.T[0]) if (bt.T == bt.T[0]).all() else bt.T
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt)
-    c, b, h, u0, w = t(bt.c), t(bt.b), t(bt.h), t(bt.u0), t(bt.w)
+    S0 = bt.total_steps
+    rows = bt.wrow is not None
+    c, b, h = t(np.reshape(bt.c, (S0, -1))), t(np.reshape(bt.b, (-1,))), t(bt.h)
+    u0 = t(np.reshape(bt.u0, (bt.n_inst, -1)))
+    w = t(pack_weights(bt)) if rows else t(bt.w)
     tuned = None
     if tune:
         from paper_2410_06074_amd import autotune
@@ -147,7 +180,7 @@ def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0, graph=
         block, max_blocks = tuned["block"], tuned["max_blocks"]
         log("  autotuned:", {k: v for k, v in tuned.items() if k != "candidates"})
     plan = Plan(bt.R, bt.n_init, bt.n_inst, steps_arg, mode=mode, chunk=chunk, chunk_upper=chunk_upper,
-                block=block, max_blocks=max_blocks)
+                block=block, max_blocks=max_blocks, variables=bt.V, equations=bt.Q, row_weights=rows)
     S, K = plan.total_steps, plan.k
     y = torch.empty((S, K), dtype=dt, device=dev)
     fac, ws = plan.new_factor(dev), plan.new_workspace(dev)
@@ -155,7 +188,7 @@ def run_mode(bt, mode, steps, warmup, sample_idx, chunk=0, chunk_upper=0, graph=
     du0, dw = torch.empty_like(u0), torch.empty_like(w)
     plan.forward(c, b, h, u0, w, y, fac, ws)
     gy = torch.zeros_like(y)
-    gy[:, 0] = 2.0 * y[:, 0]
+    gy[:, 0::bt.k] = 2.0 * y[:, 0::bt.k]       # loss: sum of squares of every variable's value
     torch.cuda.synchronize()
 
     def step():
@@ -349,7 +382,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="h", choices=["h", "c1", "c2", "c3", "c4"])
+    ap.add_argument("--config", default="h", choices=["h", "c1", "c2", "c3", "c4", "hw", "v2", "v3"])
     ap.add_argument("--mode", default="fp64r", choices=["fp64", "fp64r", "fp32r"])
     ap.add_argument("--side-modes", default="fp64,fp32r", help="extra modes measured (comma list, '' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -402,6 +435,7 @@ def main():
                r["levels"]))
     head = results[args.mode]
     value = bt.total_steps / (head["ms"] * 1e-3)
+    scalar_form = bt.V == 1 and bt.Q == 1 and bt.wrow is None   # the paper's schedule model covers these
     line = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -421,18 +455,19 @@ def main():
         "roofline": roofline(head),
         "step_hbm_bytes_algorithmic": int(head["step_bytes"]),
         "step_bandwidth_frac": round(head["step_bytes"] / (head["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "comp_bytes_per_step": comp_bytes_per_step(bt.R, args.mode),
-        "comp_frac": round(value * comp_bytes_per_step(bt.R, args.mode) / 1e9 / HBM_PEAK_GBS, 4),
+        "comp_bytes_per_step": comp_bytes_per_step(bt, args.mode),
+        "comp_frac": round(value * comp_bytes_per_step(bt, args.mode) / 1e9 / HBM_PEAK_GBS, 4),
         "sampled_instances": sample,
         "sampled_cond_M": head["kappa"],
-        "sched_bytes_per_step": sched_bytes_per_step(bt.R, args.mode, head["refine"]),
-        "sched_frac": round(value * sched_bytes_per_step(bt.R, args.mode, head["refine"]) / 1e9 / HBM_PEAK_GBS, 4),
+        "sched_bytes_per_step": sched_bytes_per_step(bt.R, args.mode, head["refine"]) if scalar_form else None,
+        "sched_frac": round(value * sched_bytes_per_step(bt.R, args.mode, head["refine"]) / 1e9 / HBM_PEAK_GBS, 4)
+                      if scalar_form else None,
         "modes": {m: {"steps_per_s": round(bt.total_steps / (r["ms"] * 1e-3), 1), "ms_per_step": round(r["ms"], 5),
                       "err_vs_fp64_oracle": r["err"], "refine_steps": r["refine"], "chunk": r["chunk"],
                       "roofline_frac": roofline(r)["frac"], "eager_ms_per_step": round(r["ms_eager"], 5),
                       "timing": "hipGraph replay" if r["graph"] else "eager launches",
                       "step_bandwidth_frac": round(r["step_bytes"] / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                      "sched_frac": round(bt.total_steps / (r["ms"] * 1e-3) * sched_bytes_per_step(bt.R, m, r["refine"])
+                      "sched_frac": None if not scalar_form else round(bt.total_steps / (r["ms"] * 1e-3) * sched_bytes_per_step(bt.R, m, r["refine"])
                                           / 1e9 / HBM_PEAK_GBS, 4),
                       "traced_ms_per_step": round(r["ms_traced"], 5)}
                   for m, r in results.items()},

@@ -22,16 +22,46 @@ namespace {
 constexpr int WAVE = 64;
 constexpr int GPW = WAVE / GROUP;   // chunks (groups) per wavefront
 
-// The lane's group: its row r and a broadcast within the 16 lanes.
+// Row J of the lane's 16-lane group (a DPP row of the wave): a
+// row_newbcast data-parallel move, one VALU instruction per 32-bit half.
+template <int J>
+__device__ __forceinline__ double row_bcast(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, 0x150 + J, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, 0x150 + J, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// The lane's group: its row r and a broadcast within the 16 lanes.  j is a
+// compile-time constant at every call (unrolled loops), so the switch folds
+// to the one move.
 struct GpuGrp {
   int r;
-  int base;
-  __device__ double bcast(double v, int j) const { return __shfl(v, base + j, WAVE); }
+  __device__ __forceinline__ double bcast(double v, int j) const {
+    switch (j) {
+      case 0: return row_bcast<0>(v);
+      case 1: return row_bcast<1>(v);
+      case 2: return row_bcast<2>(v);
+      case 3: return row_bcast<3>(v);
+      case 4: return row_bcast<4>(v);
+      case 5: return row_bcast<5>(v);
+      case 6: return row_bcast<6>(v);
+      case 7: return row_bcast<7>(v);
+      case 8: return row_bcast<8>(v);
+      case 9: return row_bcast<9>(v);
+      case 10: return row_bcast<10>(v);
+      case 11: return row_bcast<11>(v);
+      case 12: return row_bcast<12>(v);
+      case 13: return row_bcast<13>(v);
+      case 14: return row_bcast<14>(v);
+      default: return row_bcast<15>(v);
+    }
+  }
 };
 
 __device__ __forceinline__ GpuGrp grp() {
   const int lane = threadIdx.x & (WAVE - 1);
-  return GpuGrp{lane & (GROUP - 1), lane & ~(GROUP - 1)};
+  return GpuGrp{lane & (GROUP - 1)};
 }
 
 // Wave index (XCD-aware, as in smnn_kernels.hip) and the static tile schedule.

@@ -208,11 +208,23 @@ def config(name: str, seed: int | None = None, n_inst: int | None = None, T: int
         w_gov, w_init, w_smooth each log-uniform on [0.1, 10].
     c4  4 x 8 = 32 instances, R=2, T = 1,000,000, as c0.
     h   512 x 3 = 1536 instances, R=2, T = 10,000, as c1 (throughput headline).
+    hw  as h with per-row weights log-uniform on [0.5, 2] (App. A.1's W).
+    v2  1536 instances of two coupled order-1 variables with two governing
+        equations per point, T = 10,000 (coupled_batch).
+    v3  512 instances of three coupled order-2 variables with three governing
+        equations per point (the Lorenz batch of Sec. 5.1 as one coupled
+        system per window), T = 1,000 (coupled_batch).
     """
-    seeds = {"c0": 0, "c1": 1, "c2": 2, "c3": 3, "c4": 4, "h": 5}
+    seeds = {"c0": 0, "c1": 1, "c2": 2, "c3": 3, "c4": 4, "h": 5, "hw": 6, "v2": 7, "v3": 8}
     if name not in seeds:
         raise KeyError(name)
     sd = seeds[name] if seed is None else seed
+    if name == "hw":
+        return gaussian_batch(n_inst or 1536, T or 10_000, R=2, seed=sd, name=name, per_row=True)
+    if name == "v2":
+        return coupled_batch(n_inst or 1536, T or 10_000, R=1, V=2, Q=2, seed=sd, name=name)
+    if name == "v3":
+        return coupled_batch(n_inst or 512, T or 1000, R=2, V=3, Q=3, seed=sd, name=name)
     if name in ("c0", "c1", "c4", "h"):
         defaults = {"c0": (1, 64), "c1": (1536, 1000), "c4": (32, 1_000_000), "h": (1536, 10_000)}
         N, TT = defaults[name]
