@@ -21,6 +21,12 @@ namespace {
 
 constexpr int WAVE = 64;
 constexpr int GPW = WAVE / GROUP;   // chunks (groups) per wavefront
+// One wave per SIMD: the rows of a 9 x 9 block step need ~450 registers;
+// held to two waves per SIMD the kernels spill ~1 KB per lane to scratch and
+// measured 2.9x slower (27.3 vs 9.4 ms per fp64r step, 512 x 1000, V = 3).
+#ifndef SMNN_WIDE_MIN_BLOCKS
+#define SMNN_WIDE_MIN_BLOCKS 1
+#endif
 
 // Row J of the lane's 16-lane group (a DPP row of the wave): a
 // row_newbcast data-parallel move, one VALU instruction per 32-bit half.
@@ -142,7 +148,7 @@ __device__ __forceinline__ Where where(const LevelDev& lv, int64_t tile) {
 
 // ------------------------------------------------------------------ reduces
 template <int K, int L, class TIO, int RHS, bool WREC, class F>
-__global__ void __launch_bounds__(256, 1) wk_reduce0(LevelDev l0, LevelDev l1, Level0Args a) {
+__global__ void __launch_bounds__(256, SMNN_WIDE_MIN_BLOCKS) wk_reduce0(LevelDev l0, LevelDev l1, Level0Args a) {
   const GpuGrp G = grp();
   const int64_t tiles = (l0.chunks + GPW - 1) / GPW;
   for (int64_t tw = wave_id(a); tw < tiles; tw += a.nwaves) {
@@ -162,7 +168,7 @@ __global__ void __launch_bounds__(256, 1) wk_reduce0(LevelDev l0, LevelDev l1, L
 }
 
 template <int K, int L, bool WREC>
-__global__ void __launch_bounds__(256, 1) wk_reduceN(LevelDev lv, LevelDev nx, Level0Args a, int level) {
+__global__ void __launch_bounds__(256, SMNN_WIDE_MIN_BLOCKS) wk_reduceN(LevelDev lv, LevelDev nx, Level0Args a, int level) {
   const GpuGrp G = grp();
   const int64_t tiles = (lv.chunks + GPW - 1) / GPW;
   for (int64_t tw = wave_id(a); tw < tiles; tw += a.nwaves) {
@@ -183,7 +189,7 @@ __global__ void __launch_bounds__(256, 1) wk_reduceN(LevelDev lv, LevelDev nx, L
 
 // ----------------------------------------------------- back-substitutions
 template <int K, int L>
-__global__ void __launch_bounds__(256, 1) wk_backsubN(LevelDev lv, LevelDev nx, bool has_next, Level0Args a,
+__global__ void __launch_bounds__(256, SMNN_WIDE_MIN_BLOCKS) wk_backsubN(LevelDev lv, LevelDev nx, bool has_next, Level0Args a,
                                                       int level) {
   const GpuGrp G = grp();
   const int r = G.r;
@@ -216,7 +222,7 @@ __global__ void __launch_bounds__(256, 1) wk_backsubN(LevelDev lv, LevelDev nx, 
 }
 
 template <int K, int L, class TIO, int RHS, int OUT, class F>
-__global__ void __launch_bounds__(256, 1) wk_backsub0(LevelDev l0, LevelDev l1, bool has_next, Level0Args a) {
+__global__ void __launch_bounds__(256, SMNN_WIDE_MIN_BLOCKS) wk_backsub0(LevelDev l0, LevelDev l1, bool has_next, Level0Args a) {
   constexpr bool ADD = (RHS == RHS_RESID || RHS == RHS_GRESID);
   const GpuGrp G = grp();
   const int r = G.r;
