@@ -30,7 +30,7 @@ struct smnn_plan {
   size_t factor_bytes = 0, workspace_bytes = 0;
   size_t buf_off[2] = {0, 0}, dwp_off = 0, info_off = 0, queue_off = 0;
   void* meta = nullptr;          // device metadata (chunk_inst, chunk_off, node_off of every level)
-  const int32_t* order = nullptr;  // in meta: instances by decreasing T
+  const int32_t* order = nullptr;  // in meta: instances by decreasing T (ragged batches only)
   // launch tracing (smnn_trace_enable); mutable: recorded during const calls
   mutable std::vector<hipEvent_t> ev;
   mutable std::vector<smnn_trace_record> rec;
@@ -408,7 +408,9 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
     p->lev[l].nodes = lv[l].nodes;
   }
   p->lev[0].chunk_step = reinterpret_cast<const int64_t*>(m + cs);
-  p->order = reinterpret_cast<const int32_t*>(m + od);
+  // (no order for equal lengths: those launches alternate their direction)
+  const bool ragged = std::any_of(T.begin(), T.end(), [&](int64_t t) { return t != T[0]; });
+  p->order = ragged ? reinterpret_cast<const int32_t*>(m + od) : nullptr;
   *out = p;
   return SMNN_OK;
 }

@@ -52,7 +52,8 @@ struct Level0Args {
   uint32_t* queue_base = nullptr;     //   queue_slots counters zeroed at the start of the call,
   int queue_slots = 0;                //   handed out in launch order (queue_next)
   mutable int queue_next = 0;
-  const int32_t* order = nullptr;  // [N] instances by decreasing T (one-wave-per-instance launches)
+  const int32_t* order = nullptr;  // [N] instances by decreasing T (one-wave-per-instance launches
+                                   // of ragged batches; null: equal lengths)
   mutable int rev = 0;       // 1: take the tiles (instances) in decreasing order; the
                              // host flips it before every launch of a call
   int wpb = 1;               // waves per workgroup of the launch (set by the launcher)

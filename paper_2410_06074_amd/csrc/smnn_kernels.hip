@@ -83,11 +83,15 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 // (a capped grid) carry a device work queue instead, a counter that every
 // wave increments to claim its next tile until the tiles run out, so waves
 // that finish early take more.  Every lane of a wave calls these at the
-// same point (wave-uniform control flow), lane 0 claims for the wave.
+// same point (wave-uniform control flow), lane 0 claims for the wave and
+// the claim is read back into a scalar register (readfirstlane, not a lane
+// shuffle), so that the tile index stays wave-uniform to the compiler as in
+// the static schedule: addresses derived from it stay scalar and the tile
+// loop is not treated as divergent.
 __device__ __forceinline__ int64_t claim_tile(const Level0Args& a) {
   int v = 0;
   if (lane_id() == 0) v = static_cast<int>(atomicAdd(a.queue, 1u));
-  return static_cast<int64_t>(static_cast<uint32_t>(__shfl(v, 0, WAVE)));
+  return static_cast<int64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(v)));
 }
 __device__ __forceinline__ int64_t first_tile(const Level0Args& a) {
   return a.queue ? claim_tile(a) : wave_id(a);
@@ -700,8 +704,9 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_top(LevelDev lv, Level0
   double* base = reinterpret_cast<double*>(smem) + (threadIdx.x / WAVE) * (TopCaps<L>::nodes * PER);
   const int lane = lane_id();
   for (int64_t tw = first_tile(a); tw < a.N; tw = next_tile(a, tw)) {
-    // instances longest first (the plan's order), so the longest chains start first
-    const int64_t inst = a.order ? a.order[tw] : tw;
+    // ragged batches: instances longest first (the plan's order), so the
+    // longest chains start first; equal lengths: alternate the direction
+    const int64_t inst = a.order ? a.order[tw] : (a.rev ? a.N - 1 - tw : tw);
     const int64_t off = lv.node_off[inst];
     const int64_t n = lv.node_off[inst + 1] - off;
     const int64_t c0 = lv.chunk_off[inst];
