@@ -112,26 +112,67 @@ struct Reads {
 };
 
 // Byte layout of one wave's LDS slice: ROWS steps of each array read, every
-// array 16-byte aligned.  A tile spans at most 64 chunks of L steps plus the
-// step before and the step after.  Rows of c hold QE K values, rows of b and
-// of the governing weights QE.
-template <int K, int L, class TIO, int RHS, int OUT, class F = FormScalar>
+// array 16-byte aligned.  A tile spans at most CH chunks (one per lane, 64
+// unless TileChunks below says fewer) of L steps plus the step before and
+// the step after.  Rows of c hold QE K values, rows of b and of the
+// governing weights QE.
+template <int K, int L, class TIO, int RHS, int OUT, class F = FormScalar, int CH = WAVE>
 struct Stage {
   using RD = Reads<RHS, OUT>;
-  static constexpr int ROWS = WAVE * L + 2;
   static constexpr size_t al(size_t b) { return (b + 15) / 16 * 16; }
-  static constexpr size_t ROW_K = al(sizeof(TIO) * K * ROWS), ROW_1 = al(sizeof(TIO) * ROWS);
-  static constexpr size_t ROW_C = al(sizeof(TIO) * F::QE * K * ROWS), ROW_D = al(sizeof(TIO) * F::QE * ROWS);
-  static constexpr size_t C = 0;
-  static constexpr size_t S = C + ROW_C;
-  static constexpr size_t D = S + ROW_1;
-  static constexpr size_t G = D + (RD::d ? ROW_D : 0);
-  static constexpr size_t V = G + (RD::g ? ROW_K : 0);
+  struct Layout {
+    size_t C, S, D, G, V, WG, WS, BYTES;
+  };
+  // slot offsets of a slice of `rows` rows
+  static constexpr Layout layout(int rows) {
+    const size_t row_k = al(sizeof(TIO) * K * rows), row_1 = al(sizeof(TIO) * rows);
+    const size_t row_c = al(sizeof(TIO) * F::QE * K * rows), row_d = al(sizeof(TIO) * F::QE * rows);
+    Layout o{};
+    o.C = 0;
+    o.S = o.C + row_c;
+    o.D = o.S + row_1;
+    o.G = o.D + (RD::d ? row_d : 0);
+    o.V = o.G + (RD::g ? row_k : 0);
+    o.WG = o.V + (RD::v ? row_k : 0);
+    o.WS = o.WG + (F::WROW ? row_d : 0);
+    o.BYTES = o.WS + (F::WROW ? row_1 : 0);
+    return o;
+  }
+  static constexpr int ROWS = CH * L + 2;
+  static constexpr size_t C = layout(ROWS).C;
+  static constexpr size_t S = layout(ROWS).S;
+  static constexpr size_t D = layout(ROWS).D;
+  static constexpr size_t G = layout(ROWS).G;
+  static constexpr size_t V = layout(ROWS).V;
   static constexpr size_t Y = G;   // dl/dy is read by the forward sweep only
-  static constexpr size_t WG = V + (RD::v ? ROW_K : 0);
-  static constexpr size_t WS = WG + (F::WROW ? ROW_D : 0);
-  static constexpr size_t BYTES = WS + (F::WROW ? ROW_1 : 0);
+  static constexpr size_t WG = layout(ROWS).WG;
+  static constexpr size_t WS = layout(ROWS).WS;
+  static constexpr size_t BYTES = layout(ROWS).BYTES;
 };
+
+// Chunks per tile of a level-0 kernel.  The gradient back-substitution and
+// the fused back-substitution + reduce of 3 x 3 blocks hold two waves per
+// SIMD by their registers, eight per CU; with one chunk per lane their
+// slices of the gradient and of the adjoint-residual variants exceed an
+// eighth of the CU's 160 KB of LDS, so LDS would admit only seven.  Those
+// take the largest tile whose slice fits an eighth (64 -> 57 chunks for the
+// gradient pass, 63 for the fused adjoint pass, at chunk 4 in FP64 and at
+// chunk 8 with float I/O; lanes beyond it idle), unless that is under 48;
+// measured 3 % and 7 % faster.  Every other kernel takes 64.
+constexpr size_t LDS_PER_CU = 160 * 1024;
+template <int K, int L, class TIO, int RHS, int OUT, class F, bool TWO_PER_SIMD>
+struct TileChunks {
+  static constexpr int fit() {   // 64 when it would take fewer than 48 (a quarter of the lanes idle)
+    int ch = WAVE;
+    while (ch > 3 * WAVE / 4 && Stage<K, L, TIO, RHS, OUT, F>::layout(ch * L + 2).BYTES > LDS_PER_CU / 8) --ch;
+    return Stage<K, L, TIO, RHS, OUT, F>::layout(ch * L + 2).BYTES > LDS_PER_CU / 8 ? WAVE : ch;
+  }
+  static constexpr int value = TWO_PER_SIMD && K == 3 ? fit() : WAVE;
+};
+template <int K, int L, class TIO, int RHS, int OUT, class F>
+using B0Chunks = TileChunks<K, L, TIO, RHS, OUT, F, OUT == OUT_GRAD>;
+template <int K, int L, class TIO, int ROUT, class F>
+using BRChunks = TileChunks<K, L, TIO, ROUT, OUT_STORE, F, true>;
 
 // Wave-cooperative copy of rows [lo, hi) of an array with w elements per row
 // into LDS (4 bytes per lane per load; the loads write LDS directly and are
@@ -149,10 +190,10 @@ __device__ __forceinline__ void stage_rows(const void* src, int w, int64_t lo, i
 
 // Per-row weights: the governing weights (QE per row) and the smoothness
 // weight of each step.
-template <int K, int L, class TIO, int RHS, int OUT, class F>
+template <int K, int L, class TIO, int RHS, int OUT, class F, int CH = WAVE>
 __device__ __forceinline__ void stage_weights(const Level0Args& a, int64_t lo, int64_t hi, unsigned char* sl,
                                               int lane) {
-  using ST = Stage<K, L, TIO, RHS, OUT, F>;
+  using ST = Stage<K, L, TIO, RHS, OUT, F, CH>;
   if constexpr (F::WROW) {
     stage_rows<TIO>(a.wg, F::QE, lo, hi, sl + ST::WG, lane);
     stage_rows<TIO>(a.ws, 1, lo, hi, sl + ST::WS, lane);
@@ -160,17 +201,17 @@ __device__ __forceinline__ void stage_weights(const Level0Args& a, int64_t lo, i
 }
 
 // Copies rows [lo, hi) of every array the variant reads into the slice.
-template <int K, int L, class TIO, int RHS, int OUT, class F>
+template <int K, int L, class TIO, int RHS, int OUT, class F, int CH = WAVE>
 __device__ __forceinline__ void stage_tile(const Level0Args& a, int64_t lo, int64_t hi, unsigned char* sl,
                                            int lane) {
-  using ST = Stage<K, L, TIO, RHS, OUT, F>;
+  using ST = Stage<K, L, TIO, RHS, OUT, F, CH>;
   using RD = Reads<RHS, OUT>;
   stage_rows<TIO>(a.c, F::QE * K, lo, hi, sl + ST::C, lane);
   stage_rows<TIO>(a.s, 1, lo, hi, sl + ST::S, lane);
   if (RD::d) stage_rows<TIO>(a.d, F::QE, lo, hi, sl + ST::D, lane);
   if (RD::g) stage_rows<TIO>(a.g, K, lo, hi, sl + ST::G, lane);
   if (RD::v) stage_rows<TIO>(a.v, K, lo, hi, sl + ST::V, lane);
-  stage_weights<K, L, TIO, RHS, OUT, F>(a, lo, hi, sl, lane);
+  stage_weights<K, L, TIO, RHS, OUT, F, CH>(a, lo, hi, sl, lane);
 }
 
 // Rows of the tile of chunks [g0, g1): from the step before the first chunk
@@ -216,10 +257,10 @@ __device__ __forceinline__ Inst<K> load_inst(const Level0Args& a, int64_t i) {
 
 // Source reading the wave's LDS slice: node i of the instance at global
 // row off is slice row off - lo + i.
-template <int K, int L, class TIO, int RHS, int OUT, class F, int LRHS = RHS>
+template <int K, int L, class TIO, int RHS, int OUT, class F, int LRHS = RHS, int CH = WAVE>
 __device__ __forceinline__ Src0<K, TIO, RHS, F> make_src0_lds(const Level0Args& a, int64_t i, int64_t off,
                                                               int64_t n, int64_t lo, unsigned char* sl) {
-  using ST = Stage<K, L, TIO, LRHS, OUT, F>;   // slice layout of the variant LRHS
+  using ST = Stage<K, L, TIO, LRHS, OUT, F, CH>;   // slice layout of the variant LRHS
   Src0<K, TIO, RHS, F> S;
   S.c = reinterpret_cast<const TIO*>(sl + ST::C);
   S.s = reinterpret_cast<const TIO*>(sl + ST::S);
@@ -409,19 +450,20 @@ __global__ void __launch_bounds__(256, (Backsub0Waves<K, L, OUT>::value)) k_back
                                                                                      bool has_next, Level0Args a) {
   constexpr bool ADD = (RHS == RHS_RESID || RHS == RHS_GRESID);
   constexpr int QE = F::QE, NI = F::V;   // governing equations per point; variables per initial point
-  using ST = Stage<K, L, TIO, RHS, OUT, F>;
+  constexpr int CH = B0Chunks<K, L, TIO, RHS, OUT, F>::value;   // chunks per tile
+  using ST = Stage<K, L, TIO, RHS, OUT, F, CH>;
   extern __shared__ __align__(16) unsigned char smem[];
   unsigned char* sl = smem + (threadIdx.x / WAVE) * ST::BYTES;
   const int lane = lane_id();
   const int64_t G = l0.chunks;
-  const int64_t tiles = (G + WAVE - 1) / WAVE;
+  const int64_t tiles = (G + CH - 1) / CH;
   for (int64_t tw = first_tile(a); tw < tiles; tw = next_tile(a, tw)) {
     const int64_t tile = a.rev ? tiles - 1 - tw : tw;
-    const int64_t g0 = tile * WAVE;
-    const int64_t g1 = g0 + WAVE < G ? g0 + WAVE : G;
+    const int64_t g0 = tile * CH;
+    const int64_t g1 = g0 + CH < G ? g0 + CH : G;
     // chunk metadata first: its loads then return ahead of the staged tile
     const int64_t g = g0 + lane;
-    const bool valid = g < G;
+    const bool valid = lane < CH && g < G;
     const int64_t gg = valid ? g : G - 1;
     const int64_t inst = l0.chunk_inst[gg];
     int64_t lo, hi, r0, r1;
@@ -430,8 +472,8 @@ __global__ void __launch_bounds__(256, (Backsub0Waves<K, L, OUT>::value)) k_back
     const int64_t off = l0.node_off[inst];
     const int64_t n = l0.node_off[inst + 1] - off;
     const int64_t up0 = (has_next ? l1.node_off : l0.node_off)[inst];   // unconditional load
-    const auto src = make_src0_lds<K, L, TIO, RHS, OUT, F>(a, inst, off, n, lo, sl);
-    stage_tile<K, L, TIO, RHS, OUT, F>(a, lo, hi, sl, lane);
+    const auto src = make_src0_lds<K, L, TIO, RHS, OUT, F, RHS, CH>(a, inst, off, n, lo, sl);
+    stage_tile<K, L, TIO, RHS, OUT, F, CH>(a, lo, hi, sl, lane);
     const int64_t j = gg - j0;
     const int64_t up = has_next ? up0 : 0;
     const ChunkGeom geo = chunk_geom(j, n, L);
@@ -529,15 +571,16 @@ __global__ void __launch_bounds__(256, (Backsub0Waves<K, L, OUT>::value)) k_back
 // of the refinement solve that follows it (RIN = beta, ROUT = residual; or
 // RIN = dl/dy, ROUT = adjoint residual).  The new iterate stays in the LDS
 // slice, where the residual reduce reads it, so that reduce re-reads no
-// input from HBM.  A tile owns 62 chunks; lane 0 back-substitutes and
-// reduces the previous tile's last owned chunk (each separator is combined
-// from the chunks on both of its sides) and lane 63 back-substitutes the
-// next tile's first chunk (the residual at a chunk's right separator needs
-// the iterate one step past it).
+// input from HBM.  A tile owns CH - 2 chunks (62 with one chunk per lane);
+// lane 0 back-substitutes and reduces the previous tile's last owned chunk
+// (each separator is combined from the chunks on both of its sides) and
+// lane CH - 1 back-substitutes the next tile's first chunk (the residual at
+// a chunk's right separator needs the iterate one step past it).
 template <int K, int L, class TIO, int RIN, int ROUT, class F>
 __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDev l0, LevelDev l1, Level0Args a) {
-  using ST = Stage<K, L, TIO, ROUT, OUT_STORE, F>;   // c, h, (b | dl/dy) staged; the iterate in the v slot
-  constexpr int OWN = WAVE - 2;
+  constexpr int CH = BRChunks<K, L, TIO, ROUT, F>::value;   // chunks per tile
+  using ST = Stage<K, L, TIO, ROUT, OUT_STORE, F, CH>;   // c, h, (b | dl/dy) staged; the iterate in the v slot
+  constexpr int OWN = CH - 2;
   extern __shared__ __align__(16) unsigned char smem[];
   unsigned char* sl = smem + (threadIdx.x / WAVE) * ST::BYTES;
   TIO* it = reinterpret_cast<TIO*>(sl + ST::V);
@@ -563,12 +606,12 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDe
     const int64_t n = l0.node_off[inst + 1] - off;
     const int64_t up0 = (l1.node_off ? l1.node_off : l0.node_off)[inst];
     const int64_t c1 = (l1.chunk_off ? l1.chunk_off : l0.chunk_off)[inst];
-    const auto src = make_src0_lds<K, L, TIO, RIN, OUT_STORE, F, ROUT>(a, inst, off, n, lo, sl);
+    const auto src = make_src0_lds<K, L, TIO, RIN, OUT_STORE, F, ROUT, CH>(a, inst, off, n, lo, sl);
     stage_rows<TIO>(a.c, F::QE * K, lo, hi, sl + ST::C, lane);
     stage_rows<TIO>(a.s, 1, lo, hi, sl + ST::S, lane);
     if (RIN == RHS_BETA) stage_rows<TIO>(a.d, F::QE, lo, hi, sl + ST::D, lane);
     if (RIN == RHS_G) stage_rows<TIO>(a.g, K, lo, hi, sl + ST::G, lane);
-    stage_weights<K, L, TIO, ROUT, OUT_STORE, F>(a, lo, hi, sl, lane);
+    stage_weights<K, L, TIO, ROUT, OUT_STORE, F, CH>(a, lo, hi, sl, lane);
     const int64_t j = gg - j0;
     const ChunkGeom geo = chunk_geom(j, n, L);
     double xl[K], xr[K], xs[L][K];
@@ -848,9 +891,9 @@ int64_t grid_for(int64_t tiles, const Launch& cfg) {
 
 // Grid, workgroup and dynamic LDS of a level-0 launch: as many waves per
 // workgroup as cfg.block asks for and the per-workgroup LDS limit allows.
-template <int K, int L, class TIO, int RHS, int OUT, class F>
+template <int K, int L, class TIO, int RHS, int OUT, class F, int CH = WAVE>
 bool level0_grid(int64_t tiles, const Launch& cfg, dim3& grid, dim3& block, size_t& lds) {
-  constexpr size_t wb = Stage<K, L, TIO, RHS, OUT, F>::BYTES;
+  constexpr size_t wb = Stage<K, L, TIO, RHS, OUT, F, CH>::BYTES;
   const int64_t fit = static_cast<int64_t>(cfg.lds_max) / static_cast<int64_t>(wb);
   if (fit < 1) return false;
   int wpb = cfg.block / WAVE;
@@ -881,10 +924,11 @@ hipError_t launch_r0(const LevelDev& l0, const LevelDev& l1, const Level0Args& a
 template <int K, int L, class TIO, int RHS, int OUT, class F>
 hipError_t launch_b0(const LevelDev& l0, const LevelDev* l1, const Level0Args& a, const Launch& cfg,
                      hipStream_t st) {
-  const int64_t tiles = (l0.chunks + WAVE - 1) / WAVE;
+  constexpr int CH = B0Chunks<K, L, TIO, RHS, OUT, F>::value;
+  const int64_t tiles = (l0.chunks + CH - 1) / CH;
   dim3 grid, block;
   size_t lds;
-  if (!level0_grid<K, L, TIO, RHS, OUT, F>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
+  if (!level0_grid<K, L, TIO, RHS, OUT, F, CH>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
   const LevelDev nx = l1 ? *l1 : LevelDev{};
   Level0Args b = a;
   b.wpb = static_cast<int>(block.x) / WAVE;
@@ -896,10 +940,11 @@ hipError_t launch_b0(const LevelDev& l0, const LevelDev* l1, const Level0Args& a
 template <int K, int L, class TIO, int RIN, int ROUT, class F>
 hipError_t launch_br0(const LevelDev& l0, const LevelDev& l1, const Level0Args& a, const Launch& cfg,
                       hipStream_t st) {
-  const int64_t tiles = (l0.chunks + WAVE - 3) / (WAVE - 2);
+  constexpr int CH = BRChunks<K, L, TIO, ROUT, F>::value;
+  const int64_t tiles = (l0.chunks + CH - 3) / (CH - 2);
   dim3 grid, block;
   size_t lds;
-  if (!level0_grid<K, L, TIO, ROUT, OUT_STORE, F>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
+  if (!level0_grid<K, L, TIO, ROUT, OUT_STORE, F, CH>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
   Level0Args b = a;
   b.wpb = static_cast<int>(block.x) / WAVE;
   b.nwaves = static_cast<int64_t>(grid.x) * b.wpb;
@@ -956,8 +1001,9 @@ hipError_t backsub_reduce0_t(int rhs_in, const LevelDev& l0, const LevelDev& l1,
 template <int K, int L, class TIO, class F>
 size_t lds_bytes_t(int rhs, int out) {
   if (out == OUT_GRAD)
-    return rhs == RHS_GRESID ? Stage<K, L, TIO, RHS_GRESID, OUT_GRAD, F>::BYTES
-                             : Stage<K, L, TIO, RHS_G, OUT_GRAD, F>::BYTES;
+    return rhs == RHS_GRESID
+               ? Stage<K, L, TIO, RHS_GRESID, OUT_GRAD, F, B0Chunks<K, L, TIO, RHS_GRESID, OUT_GRAD, F>::value>::BYTES
+               : Stage<K, L, TIO, RHS_G, OUT_GRAD, F, B0Chunks<K, L, TIO, RHS_G, OUT_GRAD, F>::value>::BYTES;
   switch (rhs) {
     case RHS_BETA: return Stage<K, L, TIO, RHS_BETA, OUT_STORE, F>::BYTES;
     case RHS_RESID: return Stage<K, L, TIO, RHS_RESID, OUT_STORE, F>::BYTES;
