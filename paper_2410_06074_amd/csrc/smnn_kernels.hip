@@ -150,29 +150,41 @@ struct Stage {
   static constexpr size_t BYTES = layout(ROWS).BYTES;
 };
 
-// Chunks per tile of a level-0 kernel.  The gradient back-substitution and
-// the fused back-substitution + reduce of 3 x 3 blocks hold two waves per
-// SIMD by their registers, eight per CU; with one chunk per lane their
-// slices of the gradient and of the adjoint-residual variants exceed an
-// eighth of the CU's 160 KB of LDS, so LDS would admit only seven.  Those
-// take the largest tile whose slice fits an eighth (64 -> 57 chunks for the
-// gradient pass, 63 for the fused adjoint pass, at chunk 4 in FP64 and at
-// chunk 8 with float I/O; lanes beyond it idle), unless that is under 48;
-// measured 3 % and 7 % faster.  Every other kernel takes 64.
+// Chunks per tile of a level-0 kernel (one per lane, 64, unless LDS would
+// hold the kernel below the occupancy its registers allow).  For 3 x 3
+// blocks: the gradient back-substitution and the fused back-substitution +
+// reduce hold WPS = 2 waves per SIMD by their registers (8 per CU); the
+// back-substitution of a refinement solve and the reduce of dl/dy hold 3
+// at chunk 4 in FP64 (12 per CU) and 2 at chunk 8 with float I/O.  With
+// one chunk per lane the slices of the gradient pass and the adjoint fused
+// pass exceed an eighth of the CU's 160 KB of LDS, and those of the other
+// two a twelfth, so LDS admitted 7, 7, 9 and 11 waves.  Each of them takes
+// the largest tile whose slice fits 1/(4 WPS) of the LDS (57, 63, 52 and
+// 60 chunks at chunk 4 in FP64; lanes beyond it idle), or 64 if that would
+// be under 48; measured 3 %, 7 %, 4 % and 3 % faster.  Every other kernel
+// takes 64.
 constexpr size_t LDS_PER_CU = 160 * 1024;
-template <int K, int L, class TIO, int RHS, int OUT, class F, bool TWO_PER_SIMD>
+template <int K, int L, class TIO, int RHS, int OUT, class F, int WPS>
 struct TileChunks {
-  static constexpr int fit() {   // 64 when it would take fewer than 48 (a quarter of the lanes idle)
+  static constexpr size_t BUDGET = WPS > 0 ? LDS_PER_CU / (4 * WPS) : LDS_PER_CU;
+  static constexpr int fit() {
     int ch = WAVE;
-    while (ch > 3 * WAVE / 4 && Stage<K, L, TIO, RHS, OUT, F>::layout(ch * L + 2).BYTES > LDS_PER_CU / 8) --ch;
-    return Stage<K, L, TIO, RHS, OUT, F>::layout(ch * L + 2).BYTES > LDS_PER_CU / 8 ? WAVE : ch;
+    while (ch > 3 * WAVE / 4 && Stage<K, L, TIO, RHS, OUT, F>::layout(ch * L + 2).BYTES > BUDGET) --ch;
+    return Stage<K, L, TIO, RHS, OUT, F>::layout(ch * L + 2).BYTES > BUDGET ? WAVE : ch;
   }
-  static constexpr int value = TWO_PER_SIMD && K == 3 ? fit() : WAVE;
+  static constexpr int value = WPS > 0 && K == 3 ? fit() : WAVE;
+};
+template <int L, class TIO>
+struct WavesRefine {   // waves per SIMD of the refinement back-substitution and the dl/dy reduce
+  static constexpr int value = L == 4 && sizeof(TIO) == 8 ? 3 : 2;
 };
 template <int K, int L, class TIO, int RHS, int OUT, class F>
-using B0Chunks = TileChunks<K, L, TIO, RHS, OUT, F, OUT == OUT_GRAD>;
+using B0Chunks = TileChunks<K, L, TIO, RHS, OUT, F,
+                            OUT == OUT_GRAD ? 2 : (RHS == RHS_RESID || RHS == RHS_GRESID ? WavesRefine<L, TIO>::value : 0)>;
+template <int K, int L, class TIO, int RHS, class F>
+using R0Chunks = TileChunks<K, L, TIO, RHS, OUT_STORE, F, RHS == RHS_G ? WavesRefine<L, TIO>::value : 0>;
 template <int K, int L, class TIO, int ROUT, class F>
-using BRChunks = TileChunks<K, L, TIO, ROUT, OUT_STORE, F, true>;
+using BRChunks = TileChunks<K, L, TIO, ROUT, OUT_STORE, F, 2>;
 
 // Wave-cooperative copy of rows [lo, hi) of an array with w elements per row
 // into LDS (4 bytes per lane per load; the loads write LDS directly and are
@@ -306,19 +318,20 @@ __device__ __forceinline__ void exchange_and_write(const Reduced<K>& red, bool w
 // ------------------------------------------------------------ level 0 reduce
 template <int K, int L, class TIO, int RHS, bool WREC, class F>
 __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduce0(LevelDev l0, LevelDev l1, Level0Args a) {
-  using ST = Stage<K, L, TIO, RHS, OUT_STORE, F>;
+  constexpr int CH = R0Chunks<K, L, TIO, RHS, F>::value;   // chunks per tile
+  using ST = Stage<K, L, TIO, RHS, OUT_STORE, F, CH>;
   extern __shared__ __align__(16) unsigned char smem[];
   unsigned char* sl = smem + (threadIdx.x / WAVE) * ST::BYTES;
   const int lane = lane_id();
   const int64_t G = l0.chunks;
-  const int64_t tiles = G > 1 ? (G - 2) / (WAVE - 1) + 1 : 1;
+  const int64_t tiles = G > 1 ? (G - 2) / (CH - 1) + 1 : 1;
   for (int64_t tw = first_tile(a); tw < tiles; tw = next_tile(a, tw)) {
     const int64_t tile = a.rev ? tiles - 1 - tw : tw;
-    const int64_t g0 = tile * (WAVE - 1);
-    const int64_t g1 = g0 + WAVE < G ? g0 + WAVE : G;
+    const int64_t g0 = tile * (CH - 1);
+    const int64_t g1 = g0 + CH < G ? g0 + CH : G;
     // chunk metadata first: its loads then return ahead of the staged tile
     const int64_t g = g0 + lane;
-    const bool valid = g < G;
+    const bool valid = lane < CH && g < G;
     const int64_t gg = valid ? g : G - 1;
     const int64_t inst = l0.chunk_inst[gg];
     int64_t lo, hi, r0, r1;
@@ -327,8 +340,8 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_reduce0(LevelDev l0, Le
     const int64_t off = l0.node_off[inst];
     const int64_t n = l0.node_off[inst + 1] - off;
     const int64_t c1 = l1.chunk_off[inst];
-    const auto src = make_src0_lds<K, L, TIO, RHS, OUT_STORE, F>(a, inst, off, n, lo, sl);
-    stage_tile<K, L, TIO, RHS, OUT_STORE, F>(a, lo, hi, sl, lane);
+    const auto src = make_src0_lds<K, L, TIO, RHS, OUT_STORE, F, RHS, CH>(a, inst, off, n, lo, sl);
+    stage_tile<K, L, TIO, RHS, OUT_STORE, F, CH>(a, lo, hi, sl, lane);
     const int64_t j = gg - j0;
     const ChunkGeom geo = chunk_geom(j, n, L);
     Reduced<K> red;
@@ -910,10 +923,11 @@ bool level0_grid(int64_t tiles, const Launch& cfg, dim3& grid, dim3& block, size
 template <int K, int L, class TIO, int RHS, bool WREC, class F>
 hipError_t launch_r0(const LevelDev& l0, const LevelDev& l1, const Level0Args& a, const Launch& cfg,
                      hipStream_t st) {
-  const int64_t tiles = l0.chunks > 1 ? (l0.chunks - 2) / (WAVE - 1) + 1 : 1;
+  constexpr int CH = R0Chunks<K, L, TIO, RHS, F>::value;
+  const int64_t tiles = l0.chunks > 1 ? (l0.chunks - 2) / (CH - 1) + 1 : 1;
   dim3 grid, block;
   size_t lds;
-  if (!level0_grid<K, L, TIO, RHS, OUT_STORE, F>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
+  if (!level0_grid<K, L, TIO, RHS, OUT_STORE, F, CH>(tiles, cfg, grid, block, lds)) return hipErrorInvalidConfiguration;
   Level0Args b = a;
   b.wpb = static_cast<int>(block.x) / WAVE;
   b.nwaves = static_cast<int64_t>(grid.x) * b.wpb;
