@@ -114,7 +114,13 @@ typedef enum {
 typedef struct smnn_plan smnn_plan; /* opaque; immutable after creation */
 
 typedef struct {
-  int32_t order;          /* R, 1..4; the block size V (R+1) must be <= 5 */
+  int32_t order;          /* R, 1..4.  Instance shapes built (else SMNN_ERR_UNSUPPORTED):
+                             one variable, Q = 1, R = 1..4, scalar or per-row weights;
+                             two variables, R = 1 with Q = 1 or 2 (scalar weights) or
+                             Q = 2 (per-row weights), R = 2 with Q = 2; three
+                             variables with Q = 3, R = 1 or 2 (per-row weights at R = 2).
+                             Blocks of more than 5 unknowns (V (R+1) = 6, 9) run on
+                             16-lane groups, chunk length 4 at every level */
   int32_t n_init;         /* initial orders fixed at each initial point, 0..R+1 */
   int64_t n_inst;         /* N >= 1 */
   const int64_t* steps;   /* HOST array [N] of T_i >= 1, or NULL: all T_i = steps_uniform */
