@@ -685,9 +685,18 @@ enum RhsMode : int {
   RHS_GRESID = 3  // f = g - A^T W A v            (refinement of the adjoint)
 };
 
+// Where element e of a per-step array with W elements per row lives: the
+// identity for arrays in global memory (and on the host); the GPU kernels
+// pass a policy that places the rows they stage in LDS (smnn_kernels.hip).
+struct IxPlain {
+  template <int W>
+  SMNN_HD static int64_t at(int64_t e) { return e; }
+};
+
 // Node data assembled on the fly from the per-step inputs of one instance.
-// TIO is the element type of the arrays in memory (double or float).
-template <int K, class TIO, int RHS, class F = FormScalar>
+// TIO is the element type of the arrays in memory (double or float); IX
+// maps the element indices of c, d, s, g, v and the per-row weights.
+template <int K, class TIO, int RHS, class F = FormScalar, class IX = IxPlain>
 struct Src0 {
   static constexpr int V = F::V, QE = F::QE, k = K / F::V;
   static_assert(k * V == K, "block size is V (R+1)");
@@ -709,15 +718,21 @@ struct Src0 {
   mutable double carry[K];
   mutable int64_t carry_node = -1;
 
-  SMNN_HD double ld(const TIO* ptr, int64_t i) const { return static_cast<double>(ptr[o + i]); }
-  SMNN_HD double ldk(const TIO* ptr, int64_t i, int r) const { return static_cast<double>(ptr[(o + i) * K + r]); }
+  SMNN_HD double ld(const TIO* ptr, int64_t i) const {
+    return static_cast<double>(ptr[IX::template at<1>(o + i)]);
+  }
+  SMNN_HD double ldk(const TIO* ptr, int64_t i, int r) const {
+    return static_cast<double>(ptr[IX::template at<K>((o + i) * K + r)]);
+  }
   // coefficient j of governing equation q at node i; its right-hand side
-  SMNN_HD double ldc(int64_t i, int q, int j) const { return static_cast<double>(c[((o + i) * QE + q) * K + j]); }
-  SMNN_HD double ldd(int64_t i, int q) const { return static_cast<double>(d[(o + i) * QE + q]); }
+  SMNN_HD double ldc(int64_t i, int q, int j) const {
+    return static_cast<double>(c[IX::template at<QE * K>(((o + i) * QE + q) * K + j)]);
+  }
+  SMNN_HD double ldd(int64_t i, int q) const { return static_cast<double>(d[IX::template at<QE>((o + i) * QE + q)]); }
   // weights (unsquared) of governing row (i, q), of the pair (i, i+1) and of
   // initial row (i, variable vv, order r)
   SMNN_HD double gov_w(int64_t i, int q) const {
-    if constexpr (F::WROW) return static_cast<double>(wg[(o + i) * QE + q]);
+    if constexpr (F::WROW) return static_cast<double>(wg[IX::template at<QE>((o + i) * QE + q)]);
     else return p.wg;
   }
   SMNN_HD double smooth_w(int64_t i) const {
@@ -890,8 +905,8 @@ struct Src0 {
 };
 
 // Level-0 solution sink: out_i = (v_i +) x_i in the I/O type.  Rows of out
-// are RS elements apart (0: K, dense).
-template <class TIO, bool ADD, int RS = 0>
+// are RS elements apart (0: K, dense); IX maps element indices as in Src0.
+template <class TIO, bool ADD, int RS = 0, class IX = IxPlain>
 struct StoreSink {
   TIO* out;        // [..][RS]: node i is row oo + i, its first K elements
   const TIO* v;    // previous iterate (ADD): node i is row vo + i
@@ -903,8 +918,8 @@ struct StoreSink {
 #pragma unroll
     for (int e = 0; e < K; ++e) {
       double val = x[e];
-      if (ADD) val += static_cast<double>(v[(vo + i) * K + e]);
-      out[(oo + i) * W + e] = static_cast<TIO>(val);
+      if (ADD) val += static_cast<double>(v[IX::template at<K>((vo + i) * K + e)]);
+      out[IX::template at<W>((oo + i) * W + e)] = static_cast<TIO>(val);
     }
   }
 };
@@ -918,8 +933,9 @@ struct StoreSink {
 // row); for the row's own weight sigma, dl/dsigma = -2 rho mu / sigma.  With
 // scalar weights dw accumulates this chunk's partial sums of the three
 // weight gradients; with per-row weights every row's is written (dwg, dws
-// like dd, ds; dwi like du0).
-template <int K, class TIO, bool ADD, class F = FormScalar>
+// like dd, ds; dwi like du0).  IX maps the element indices of the per-step
+// arrays as in Src0 (not those of du0, dwi, u, wi).
+template <int K, class TIO, bool ADD, class F = FormScalar, class IX = IxPlain>
 struct GradSink {
   static constexpr int V = F::V, QE = F::QE, k = K / F::V;
   const TIO *c, *d, *s, *y, *v;   // inputs: node i is row o + i
@@ -938,36 +954,36 @@ struct GradSink {
   double dw[3] = {0.0, 0.0, 0.0};
 
   SMNN_HD double gov_w(int64_t i, int q) const {
-    if constexpr (F::WROW) return static_cast<double>(wg[(o + i) * QE + q]);
+    if constexpr (F::WROW) return static_cast<double>(wg[IX::template at<QE>((o + i) * QE + q)]);
     else return p.wg;
   }
   SMNN_HD double smooth_w(int64_t i) const {
-    if constexpr (F::WROW) return static_cast<double>(wsm[o + i]);
+    if constexpr (F::WROW) return static_cast<double>(wsm[IX::template at<1>(o + i)]);
     else return p.ws;
   }
   SMNN_HD void lam_y(int64_t i, const double (&x)[K], double (&lam)[K], double (&yi)[K]) const {
 #pragma unroll
     for (int e = 0; e < K; ++e) {
-      lam[e] = x[e] + (ADD ? static_cast<double>(v[(o + i) * K + e]) : 0.0);
-      yi[e] = static_cast<double>(y[(o + i) * K + e]);
+      lam[e] = x[e] + (ADD ? static_cast<double>(v[IX::template at<K>((o + i) * K + e)]) : 0.0);
+      yi[e] = static_cast<double>(y[IX::template at<K>((o + i) * K + e)]);
     }
   }
   SMNN_HD void governing(int64_t i, const double (&lam)[K], const double (&yi)[K]) {
 #pragma unroll
     for (int q = 0; q < QE; ++q) {
       const double w = gov_w(i, q), wg2 = w * w;
-      double e = -static_cast<double>(d[(o + i) * QE + q]), f = 0.0;
+      double e = -static_cast<double>(d[IX::template at<QE>((o + i) * QE + q)]), f = 0.0;
 #pragma unroll
       for (int r = 0; r < K; ++r) {
-        const double cr = static_cast<double>(c[((o + i) * QE + q) * K + r]);
+        const double cr = static_cast<double>(c[IX::template at<QE * K>(((o + i) * QE + q) * K + r)]);
         e = fma(cr, yi[r], e);
         f = fma(cr, lam[r], f);
       }
 #pragma unroll
       for (int r = 0; r < K; ++r)
-        dc[((oo + i) * QE + q) * K + r] = static_cast<TIO>(-wg2 * (e * lam[r] + f * yi[r]));
-      dd[(oo + i) * QE + q] = static_cast<TIO>(wg2 * f);
-      if constexpr (F::WROW) dwg[(oo + i) * QE + q] = static_cast<TIO>(-2.0 * w * e * f);
+        dc[IX::template at<QE * K>(((oo + i) * QE + q) * K + r)] = static_cast<TIO>(-wg2 * (e * lam[r] + f * yi[r]));
+      dd[IX::template at<QE>((oo + i) * QE + q)] = static_cast<TIO>(wg2 * f);
+      if constexpr (F::WROW) dwg[IX::template at<QE>((oo + i) * QE + q)] = static_cast<TIO>(-2.0 * w * e * f);
       else dw[0] += -2.0 * p.wg * e * f;
     }
     if (i < p.t_init) {
@@ -987,7 +1003,7 @@ struct GradSink {
     }
   }
   SMNN_HD void pair(int64_t i, const double (&lam)[K], const double (&yi)[K]) {
-    const double si = static_cast<double>(s[o + i]), w = smooth_w(i);
+    const double si = static_cast<double>(s[IX::template at<1>(o + i)]), w = smooth_w(i);
     double g_s = 0.0, g_w = 0.0;
 #pragma unroll
     for (int vv = 0; vv < V; ++vv) {
@@ -1001,8 +1017,8 @@ struct GradSink {
       g_s += gs;
       g_w += gw;
     }
-    ds[oo + i] = static_cast<TIO>(g_s);
-    if constexpr (F::WROW) dws[oo + i] = static_cast<TIO>(g_w);
+    ds[IX::template at<1>(oo + i)] = static_cast<TIO>(g_s);
+    if constexpr (F::WROW) dws[IX::template at<1>(oo + i)] = static_cast<TIO>(g_w);
     else dw[2] += g_w;
   }
   // the chunk's right separator (owned; finished by the level above)
@@ -1026,8 +1042,8 @@ struct GradSink {
   }
   // the instance's last point: its step slot enters no row
   SMNN_HD void last_point(int64_t n) {
-    ds[oo + n - 1] = static_cast<TIO>(0.0);
-    if constexpr (F::WROW) dws[oo + n - 1] = static_cast<TIO>(0.0);
+    ds[IX::template at<1>(oo + n - 1)] = static_cast<TIO>(0.0);
+    if constexpr (F::WROW) dws[IX::template at<1>(oo + n - 1)] = static_cast<TIO>(0.0);
   }
   // initial points past the instance's last node (n < t_init) have no row:
   // their gradient is zero (called by the lane owning the instance's end)

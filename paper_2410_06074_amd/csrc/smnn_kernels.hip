@@ -111,22 +111,73 @@ struct Reads {
   static constexpr bool y = OUT == OUT_GRAD;   // staged after the forward sweep, over g
 };
 
+// ------------------------------------------------------------ LDS placement
+// A lane reads the rows of its own chunk, so in one LDS instruction the 64
+// lanes touch addresses W L elements apart (W elements per row, L rows per
+// chunk): 12 doubles for the 3 x 3 blocks of c at chunk 4, 4 for the step
+// sizes.  Both are multiples of 8 dwords, which puts the 64 addresses on 4
+// bank groups of the LDS.  A bank model (32 and 64 banks, 4 bytes wide; 16
+// or 32 lanes per cycle for 8-byte reads, 32 or 64 for 4-byte ones) puts
+// strides that are multiples of 8 elements at 8- to 32-way conflicts and the
+// others (4, 12, 20) at 4-way.  Arrays of the first kind are stored swizzled
+// within 256-byte blocks: element e sits at e XOR ((e >> (log2(elements per
+// block) + SH)) mod elements per block), its slot within the block XORed
+// with the block index shifted by SH (chosen per A with the same model;
+// 2-way at most).  A block holds 256 contiguous input bytes whichever the
+// swizzle, so the staging loads stay coalesced: each lane of a load fetches
+// the element its LDS position holds (the map is its own inverse).  The
+// 4-way arrays (among them all of 3 x 3 blocks at chunk 4 in FP64) stay in
+// the plain layout: measured there, the swizzle cut the conflict stalls 5x
+// but cost 15 % more VALU and 25 % more LDS instructions (each element needs
+// its own address, where the plain layout reads a row at immediate offsets
+// from one), and those kernels ran 2-9 % slower.  Where it pays is 3 x 3
+// blocks with float I/O at chunk 8 (8-way): 1-2 % faster steps on every
+// such workload measured (the 10,000-step batch, the 1,460-step AR(1)
+// batch, the long-T batch).  Other block sizes keep the plain layout: the
+// order-1 batch (2 x 2, chunk 8) ran 3-4 % slower with it and the order-3
+// ragged batch (4 x 4, whose kernels fill the register file at one wave
+// per SIMD) 3 % slower.
+constexpr int swz_shift(int A, int esz) {   // -1: plain layout
+  return A % 8 != 0 ? -1 : esz == 8 ? (A == 24 || A == 64 ? 1 : 0) : (A == 24 || A == 40 || A == 48 ? 1 : 0);
+}
+template <int K, int L, class TIO>
+struct LdsSwz {
+  static constexpr int EB = 256 / static_cast<int>(sizeof(TIO));   // elements per 256-byte block
+  static constexpr int LOG_EB = sizeof(TIO) == 8 ? 5 : 6;
+  template <int W>
+  static constexpr bool on() { return K == 3 && swz_shift(W * L, static_cast<int>(sizeof(TIO))) >= 0; }
+  template <int W>
+  __host__ __device__ __forceinline__ static int64_t at(int64_t e) {
+    if constexpr (!on<W>()) {
+      return e;
+    } else {
+      constexpr int SH = LOG_EB + swz_shift(W * L, static_cast<int>(sizeof(TIO)));
+      const int x = static_cast<int>(e);
+      return x ^ ((x >> SH) & (EB - 1));
+    }
+  }
+};
+
 // Byte layout of one wave's LDS slice: ROWS steps of each array read, every
-// array 16-byte aligned.  A tile spans at most CH chunks (one per lane, 64
+// array 16-byte aligned, swizzled arrays a whole number of 256-byte blocks
+// (their staging writes whole blocks).  A tile spans at most CH chunks (one per lane, 64
 // unless TileChunks below says fewer) of L steps plus the step before and
 // the step after.  Rows of c hold QE K values, rows of b and of the
 // governing weights QE.
 template <int K, int L, class TIO, int RHS, int OUT, class F = FormScalar, int CH = WAVE>
 struct Stage {
   using RD = Reads<RHS, OUT>;
-  static constexpr size_t al(size_t b) { return (b + 15) / 16 * 16; }
+  static constexpr size_t al(size_t b, bool swz) { return swz ? (b + 255) / 256 * 256 : (b + 15) / 16 * 16; }
+  using SW = LdsSwz<K, L, TIO>;
   struct Layout {
     size_t C, S, D, G, V, WG, WS, BYTES;
   };
   // slot offsets of a slice of `rows` rows
   static constexpr Layout layout(int rows) {
-    const size_t row_k = al(sizeof(TIO) * K * rows), row_1 = al(sizeof(TIO) * rows);
-    const size_t row_c = al(sizeof(TIO) * F::QE * K * rows), row_d = al(sizeof(TIO) * F::QE * rows);
+    const size_t row_k = al(sizeof(TIO) * K * rows, SW::template on<K>());
+    const size_t row_1 = al(sizeof(TIO) * rows, SW::template on<1>());
+    const size_t row_c = al(sizeof(TIO) * F::QE * K * rows, SW::template on<F::QE * K>());
+    const size_t row_d = al(sizeof(TIO) * F::QE * rows, SW::template on<F::QE>());
     Layout o{};
     o.C = 0;
     o.S = o.C + row_c;
@@ -186,18 +237,24 @@ using R0Chunks = TileChunks<K, L, TIO, RHS, OUT_STORE, F, RHS == RHS_G ? WavesRe
 template <int K, int L, class TIO, int ROUT, class F>
 using BRChunks = TileChunks<K, L, TIO, ROUT, OUT_STORE, F, 2>;
 
-// Wave-cooperative copy of rows [lo, hi) of an array with w elements per row
-// into LDS (4 bytes per lane per load; the loads write LDS directly and are
-// all in flight together).  Every lane of the wave calls this with the same
-// arguments; the caller waits for completion before reading.
-template <class T>
-__device__ __forceinline__ void stage_rows(const void* src, int w, int64_t lo, int64_t hi, unsigned char* dst,
-                                           int lane) {
-  const int ndw = static_cast<int>((hi - lo) * w * static_cast<int64_t>(sizeof(T)) / 4);
-  const uint32_t* gsrc = reinterpret_cast<const uint32_t*>(static_cast<const T*>(src) + lo * w);
+// Wave-cooperative copy of rows [lo, hi) of an array with W elements per row
+// into LDS in the swizzled placement of LdsSwz<K, L, T> (4 bytes per lane per
+// load; the loads write LDS directly and are all in flight together).  Load
+// b / 64 writes LDS dwords [b, b + 64) and its lanes fetch the input dwords
+// those positions hold, all within the same 256 bytes.  Every lane of the
+// wave calls this with the same arguments; the caller waits for completion
+// before reading.
+template <class T, int K, int W, int L>
+__device__ __forceinline__ void stage_rows(const void* src, int64_t lo, int64_t hi, unsigned char* dst, int lane) {
+  constexpr int DPE = static_cast<int>(sizeof(T)) / 4;   // dwords per element
+  const int ndw = static_cast<int>((hi - lo) * W * static_cast<int64_t>(sizeof(T)) / 4);
+  const uint32_t* gsrc = reinterpret_cast<const uint32_t*>(static_cast<const T*>(src) + lo * W);
   uint32_t* l = reinterpret_cast<uint32_t*>(dst);
-  for (int b = 0; b < ndw; b += WAVE)
-    if (b + lane < ndw) __builtin_amdgcn_global_load_lds(gsrc + b + lane, l + b, 4, 0, 0);
+  for (int b = 0; b < ndw; b += WAVE) {
+    const int e = static_cast<int>(LdsSwz<K, L, T>::template at<W>(b / DPE + lane / DPE));
+    const int sdw = e * DPE + lane % DPE;
+    if (sdw < ndw) __builtin_amdgcn_global_load_lds(gsrc + sdw, l + b, 4, 0, 0);
+  }
 }
 
 // Per-row weights: the governing weights (QE per row) and the smoothness
@@ -207,8 +264,8 @@ __device__ __forceinline__ void stage_weights(const Level0Args& a, int64_t lo, i
                                               int lane) {
   using ST = Stage<K, L, TIO, RHS, OUT, F, CH>;
   if constexpr (F::WROW) {
-    stage_rows<TIO>(a.wg, F::QE, lo, hi, sl + ST::WG, lane);
-    stage_rows<TIO>(a.ws, 1, lo, hi, sl + ST::WS, lane);
+    stage_rows<TIO, K, F::QE, L>(a.wg, lo, hi, sl + ST::WG, lane);
+    stage_rows<TIO, K, 1, L>(a.ws, lo, hi, sl + ST::WS, lane);
   }
 }
 
@@ -218,11 +275,11 @@ __device__ __forceinline__ void stage_tile(const Level0Args& a, int64_t lo, int6
                                            int lane) {
   using ST = Stage<K, L, TIO, RHS, OUT, F, CH>;
   using RD = Reads<RHS, OUT>;
-  stage_rows<TIO>(a.c, F::QE * K, lo, hi, sl + ST::C, lane);
-  stage_rows<TIO>(a.s, 1, lo, hi, sl + ST::S, lane);
-  if (RD::d) stage_rows<TIO>(a.d, F::QE, lo, hi, sl + ST::D, lane);
-  if (RD::g) stage_rows<TIO>(a.g, K, lo, hi, sl + ST::G, lane);
-  if (RD::v) stage_rows<TIO>(a.v, K, lo, hi, sl + ST::V, lane);
+  stage_rows<TIO, K, F::QE * K, L>(a.c, lo, hi, sl + ST::C, lane);
+  stage_rows<TIO, K, 1, L>(a.s, lo, hi, sl + ST::S, lane);
+  if (RD::d) stage_rows<TIO, K, F::QE, L>(a.d, lo, hi, sl + ST::D, lane);
+  if (RD::g) stage_rows<TIO, K, K, L>(a.g, lo, hi, sl + ST::G, lane);
+  if (RD::v) stage_rows<TIO, K, K, L>(a.v, lo, hi, sl + ST::V, lane);
   stage_weights<K, L, TIO, RHS, OUT, F, CH>(a, lo, hi, sl, lane);
 }
 
@@ -237,21 +294,21 @@ __device__ __forceinline__ void tile_rows(const LevelDev& l0, int64_t g0, int64_
   hi = r1 + 1 < S ? r1 + 1 : S;
 }
 
-// Wave-cooperative copy of rows [r0, r1) (w elements each) from a slot of the
-// wave's LDS slice (slice row = global row - lo; rows LS elements apart in
-// the slot, 0: w) to global memory: every store instruction writes 64
-// consecutive elements.
-template <class T, int LS = 0>
-__device__ __forceinline__ void unstage_rows(void* dst, int w, int64_t r0, int64_t r1, int64_t lo,
+// Wave-cooperative copy of rows [r0, r1) (W elements each) from a slot of
+// the wave's LDS slice (slice row = global row - lo; rows LS elements apart
+// in the slot, 0: W; swizzled as LdsSwz<K, L, T> places them) to global
+// memory: every store instruction writes 64 consecutive elements.
+template <class T, int K, int W, int L, int LS = 0>
+__device__ __forceinline__ void unstage_rows(void* dst, int64_t r0, int64_t r1, int64_t lo,
                                              const unsigned char* slot, int lane) {
-  T* g = static_cast<T*>(dst) + r0 * w;
-  const int n = static_cast<int>((r1 - r0) * w);
-  if (LS == 0 || LS == w) {
-    const T* l = reinterpret_cast<const T*>(slot) + (r0 - lo) * w;
-    for (int k = lane; k < n; k += WAVE) g[k] = l[k];
-  } else {
-    const T* l = reinterpret_cast<const T*>(slot) + (r0 - lo) * LS;
-    for (int k = lane; k < n; k += WAVE) g[k] = l[(k / w) * LS + k % w];
+  constexpr int RW = LS ? LS : W;
+  T* g = static_cast<T*>(dst) + r0 * W;
+  const int n = static_cast<int>((r1 - r0) * W);
+  const T* l = reinterpret_cast<const T*>(slot);
+  const int base = static_cast<int>((r0 - lo) * RW);
+  for (int k = lane; k < n; k += WAVE) {
+    const int e = base + (RW == W ? k : (k / W) * RW + k % W);
+    g[k] = l[LdsSwz<K, L, T>::template at<RW>(e)];
   }
 }
 
@@ -270,10 +327,10 @@ __device__ __forceinline__ Inst<K> load_inst(const Level0Args& a, int64_t i) {
 // Source reading the wave's LDS slice: node i of the instance at global
 // row off is slice row off - lo + i.
 template <int K, int L, class TIO, int RHS, int OUT, class F, int LRHS = RHS, int CH = WAVE>
-__device__ __forceinline__ Src0<K, TIO, RHS, F> make_src0_lds(const Level0Args& a, int64_t i, int64_t off,
+__device__ __forceinline__ Src0<K, TIO, RHS, F, LdsSwz<K, L, TIO>> make_src0_lds(const Level0Args& a, int64_t i, int64_t off,
                                                               int64_t n, int64_t lo, unsigned char* sl) {
   using ST = Stage<K, L, TIO, LRHS, OUT, F, CH>;   // slice layout of the variant LRHS
-  Src0<K, TIO, RHS, F> S;
+  Src0<K, TIO, RHS, F, LdsSwz<K, L, TIO>> S;
   S.c = reinterpret_cast<const TIO*>(sl + ST::C);
   S.s = reinterpret_cast<const TIO*>(sl + ST::S);
   S.d = reinterpret_cast<const TIO*>(sl + ST::D);
@@ -512,7 +569,7 @@ __global__ void __launch_bounds__(256, (Backsub0Waves<K, L, OUT>::value)) k_back
     // whole rows.
     if (OUT == OUT_STORE && valid) {
       // the solution goes over c, row for row (c rows hold QE K values)
-      StoreSink<TIO, ADD, QE * K> sink{reinterpret_cast<TIO*>(sl + ST::C), vs, off - lo, off - lo};
+      StoreSink<TIO, ADD, QE * K, LdsSwz<K, L, TIO>> sink{reinterpret_cast<TIO*>(sl + ST::C), vs, off - lo, off - lo};
       if (geo.has_right) sink.template node<K>(geo.b + 1, xr);   // owned right separator
       const int fail = backsub_chunk<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, xs, sink);
       if (fail) report_fail(a, inst, 0, geo.a + fail - 1);
@@ -525,11 +582,11 @@ __global__ void __launch_bounds__(256, (Backsub0Waves<K, L, OUT>::value)) k_back
       int fail = 0;
       if (valid) fail = backsub_forward<K, L>(src, geo.a, geo.b, geo.has_left, geo.has_right, xl, xr, Ls, xs);
       __builtin_amdgcn_wave_barrier();
-      stage_rows<TIO>(a.y, K, lo, hi, sl + ST::Y, lane);
+      stage_rows<TIO, K, K, L>(a.y, lo, hi, sl + ST::Y, lane);
       __builtin_amdgcn_s_waitcnt(0);
       __builtin_amdgcn_wave_barrier();
       if (valid) {
-        GradSink<K, TIO, ADD, F> sink;
+        GradSink<K, TIO, ADD, F, LdsSwz<K, L, TIO>> sink;
         sink.c = src.c; sink.d = src.d; sink.s = src.s;
         sink.wg = src.wg; sink.wsm = src.wsm; sink.wi = src.wi;
         sink.y = reinterpret_cast<const TIO*>(sl + ST::Y);
@@ -565,15 +622,15 @@ __global__ void __launch_bounds__(256, (Backsub0Waves<K, L, OUT>::value)) k_back
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     if (OUT == OUT_STORE) {
-      unstage_rows<TIO, QE * K>(a.out, K, r0, r1, lo, sl + ST::C, lane);
+      unstage_rows<TIO, K, K, L, QE * K>(a.out, r0, r1, lo, sl + ST::C, lane);
     } else {
       const int64_t s0 = r0 - (first_starts ? 0 : 1), s1 = r1 - (last_ends ? 0 : 1);
-      unstage_rows<TIO>(a.dc, QE * K, r0, r1, lo, sl + ST::C, lane);
-      unstage_rows<TIO>(a.dd, QE, r0, r1, lo, sl + ST::D, lane);
-      unstage_rows<TIO>(a.ds, 1, s0, s1, lo, sl + ST::S, lane);
+      unstage_rows<TIO, K, QE * K, L>(a.dc, r0, r1, lo, sl + ST::C, lane);
+      unstage_rows<TIO, K, QE, L>(a.dd, r0, r1, lo, sl + ST::D, lane);
+      unstage_rows<TIO, K, 1, L>(a.ds, s0, s1, lo, sl + ST::S, lane);
       if constexpr (F::WROW) {
-        unstage_rows<TIO>(a.dwg, QE, r0, r1, lo, sl + ST::WG, lane);
-        unstage_rows<TIO>(a.dws, 1, s0, s1, lo, sl + ST::WS, lane);
+        unstage_rows<TIO, K, QE, L>(a.dwg, r0, r1, lo, sl + ST::WG, lane);
+        unstage_rows<TIO, K, 1, L>(a.dws, s0, s1, lo, sl + ST::WS, lane);
       }
     }
   }
@@ -620,10 +677,10 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDe
     const int64_t up0 = (l1.node_off ? l1.node_off : l0.node_off)[inst];
     const int64_t c1 = (l1.chunk_off ? l1.chunk_off : l0.chunk_off)[inst];
     const auto src = make_src0_lds<K, L, TIO, RIN, OUT_STORE, F, ROUT, CH>(a, inst, off, n, lo, sl);
-    stage_rows<TIO>(a.c, F::QE * K, lo, hi, sl + ST::C, lane);
-    stage_rows<TIO>(a.s, 1, lo, hi, sl + ST::S, lane);
-    if (RIN == RHS_BETA) stage_rows<TIO>(a.d, F::QE, lo, hi, sl + ST::D, lane);
-    if (RIN == RHS_G) stage_rows<TIO>(a.g, K, lo, hi, sl + ST::G, lane);
+    stage_rows<TIO, K, F::QE * K, L>(a.c, lo, hi, sl + ST::C, lane);
+    stage_rows<TIO, K, 1, L>(a.s, lo, hi, sl + ST::S, lane);
+    if (RIN == RHS_BETA) stage_rows<TIO, K, F::QE, L>(a.d, lo, hi, sl + ST::D, lane);
+    if (RIN == RHS_G) stage_rows<TIO, K, K, L>(a.g, lo, hi, sl + ST::G, lane);
     stage_weights<K, L, TIO, ROUT, OUT_STORE, F, CH>(a, lo, hi, sl, lane);
     const int64_t j = gg - j0;
     const ChunkGeom geo = chunk_geom(j, n, L);
@@ -642,7 +699,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDe
     constexpr bool KEEP = K <= 3 && K * L <= 16;   // still 2 waves per SIMD
     double Ls[KEEP ? L : 1][Dim<K>::Q];
     if (valid) {
-      StoreSink<TIO, false> sink{it, nullptr, src.o, src.o};
+      StoreSink<TIO, false, 0, LdsSwz<K, L, TIO>> sink{it, nullptr, src.o, src.o};
       if (geo.has_right) sink.template node<K>(geo.b + 1, xr);
       if (lane == 0 && geo.has_left) sink.template node<K>(geo.a - 1, xl);
       int fail;
@@ -657,7 +714,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDe
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     // 2. reduce with the residual of that iterate as right-hand side
-    Src0<K, TIO, ROUT, F> rs;
+    Src0<K, TIO, ROUT, F, LdsSwz<K, L, TIO>> rs;
     rs.c = src.c; rs.d = src.d; rs.s = src.s; rs.g = src.g; rs.v = it;
     rs.wg = src.wg; rs.wsm = src.wsm; rs.wi = src.wi;
     rs.n = src.n; rs.o = src.o; rs.p = src.p; rs.u = src.u; rs.uo = src.uo;
@@ -681,7 +738,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDe
     // 3. the owned chunks' iterate out to HBM in whole rows
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
-    unstage_rows<TIO>(a.out, K, o0, o1, lo, sl + ST::V, lane);
+    unstage_rows<TIO, K, K, L>(a.out, o0, o1, lo, sl + ST::V, lane);
   }
 }
 
