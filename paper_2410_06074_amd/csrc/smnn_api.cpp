@@ -304,17 +304,20 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   std::vector<Level> lv = build_levels(T, L0, L1);
   p->S = lv[0].nodes;
   // The upper levels of a solve are short dependent chains: from the first
-  // level >= 1 at which every instance has at most 64 chunks and the level
-  // holds at most 2^19 nodes, they are solved by one launch per solve (one
-  // wave per instance), when that replaces at least two levels.  Only where
-  // that kernel keeps its state in VGPRs (block size <= 3, K * L1 <= 24):
-  // measured faster on the 1536 x 1,000 and 1536 x 10,000 batches, slower
-  // when it starts at a level of millions of nodes or spills into AGPRs.
-  if (K <= 3 && K * L1 <= 24 && top_lds_bytes(K, L1) <= static_cast<size_t>(lds_max)) {
+  // level >= 1 at which every instance has at most top_lanes(K) chunks and
+  // the level holds at most 2^19 nodes, they are solved by one launch per
+  // solve (top_lanes(K) lanes per instance), when that replaces at least two
+  // levels.  Blocks of up to 3 unknowns take it where that kernel keeps its
+  // state in VGPRs (K * L1 <= 24): measured faster on the 1536 x 1,000 and
+  // 1536 x 10,000 batches, slower when it starts at a level of millions of
+  // nodes.  Larger blocks hold a whole SIMD per wave, so they take four
+  // instances per wave (at most 16 chunks each).
+  const bool top_fits = K <= 3 ? K * L1 <= 24 : true;
+  if (!wide && top_fits && top_lds_bytes(K, L1) > 0 && top_lds_bytes(K, L1) <= static_cast<size_t>(lds_max)) {
     for (size_t l = 1; l + 1 < lv.size() && p->top == 0; ++l) {
       int64_t gmax = 0;
       for (int64_t i = 0; i < d->n_inst; ++i) gmax = std::max(gmax, lv[l].chunk_off[i + 1] - lv[l].chunk_off[i]);
-      if (gmax <= 64 && lv[l].nodes <= (int64_t(1) << 19)) p->top = static_cast<int>(l);
+      if (gmax <= top_lanes(K) && lv[l].nodes <= (int64_t(1) << 19)) p->top = static_cast<int>(l);
     }
   }
   const int Q = K * (K + 1) / 2;

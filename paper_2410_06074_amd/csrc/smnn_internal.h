@@ -119,6 +119,10 @@ hipError_t launch_backsub_reduce0(int K, int L, int form, bool f32, int rhs_in, 
                                   const LevelDev& l1, const Level0Args& a, const Launch& cfg, hipStream_t st);
 // Levels >= level of a solve in one launch, one wave per instance (every
 // instance must have at most 64 chunks at that level); writes that level's x.
+// Lanes per instance of the one-launch upper levels (k_top): one wave per
+// instance for blocks of up to 3 unknowns, 16 lanes (four instances per wave)
+// for larger blocks.
+constexpr int top_lanes(int K) { return K <= 3 ? 64 : 16; }
 hipError_t launch_top(int K, int L, int level, const LevelDev& l, const Level0Args& a, const Launch& cfg,
                       hipStream_t st);
 size_t top_lds_bytes(int K, int L);   // per wave

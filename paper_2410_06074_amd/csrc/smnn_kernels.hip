@@ -742,18 +742,23 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_backsub_reduce0(LevelDe
   }
 }
 
-// ------------------------------------- levels >= lt: one wave per instance
-// Used when every instance has at most 64 chunks at level lt.  A wave takes
-// one instance: each lane reduces one level-lt chunk from HBM, the separator
-// systems of the levels above (at most 63, 15, 3 nodes for L = 4) are kept
-// in LDS in the natural layout and reduced there while they have more than
-// one chunk, lane 0 solves the top one, and the back-substitutions come
-// down to level lt, whose solution goes to HBM.  One launch replaces the
-// reduce and back-substitution launches of levels lt and above; the upper
-// levels' records are rebuilt in LDS by every solve rather than stored.
-template <int L>
+// ------------------------------ levels >= lt: SW lanes per instance
+// Used when every instance has at most SW chunks at level lt.  A group of SW
+// lanes takes one instance (a wave takes 64 / SW of them): each lane reduces
+// one level-lt chunk from HBM, the separator systems of the levels above (at
+// most 63, 15, 3 nodes for SW = 64 and L = 4) are kept in the group's part of
+// the LDS in the natural layout and reduced there while they have more than
+// one chunk, the group's first lane solves the top one, and the
+// back-substitutions come down to level lt, whose solution goes to HBM.  One
+// launch replaces the reduce and back-substitution launches of levels lt and
+// above; the upper levels' records are rebuilt in LDS by every solve rather
+// than stored.  SW = 64 (one instance per wave) for blocks of up to 3
+// unknowns; 16 for larger blocks, whose kernel holds a whole SIMD: with one
+// instance per wave a batch of a few thousand instances would take several
+// rounds of waves.
+template <int L, int SW = WAVE>
 struct TopCaps {   // separator nodes one instance can have at LDS levels 1..3
-  static constexpr int c1 = WAVE - 1;
+  static constexpr int c1 = SW - 1;
   static constexpr int c2 = c1 > L ? (c1 + L - 1) / L - 1 : 0;
   static constexpr int c3 = c2 > L ? (c2 + L - 1) / L - 1 : 0;
   static_assert(c3 <= L, "the top is reached within three LDS levels");
@@ -767,9 +772,9 @@ struct TopLevel {
   double* x;     // [cap][K]
 };
 
-template <int K, int L>
+template <int K, int L, int SW>
 __device__ __forceinline__ TopLevel<K> top_level(double* base, int d) {
-  using C = TopCaps<L>;
+  using C = TopCaps<L, SW>;
   constexpr int REC = Dim<K>::Q + Dim<K>::KK;
   const int off = d == 1 ? 0 : (d == 2 ? C::c1 : C::c1 + C::c2);
   const int cap = d == 1 ? C::c1 : (d == 2 ? C::c2 : C::c3);
@@ -786,8 +791,9 @@ __device__ __forceinline__ int64_t top_nodes(int G, int d) {
 }
 
 // Separator m of the level just reduced = node m of LDS level `to`: lane
-// m + 1 combines the right pieces of lane m with its own left pieces.  All
-// 64 lanes must call this.
+// m + 1 of the group combines the right pieces of lane m with its own left
+// pieces.  Every lane of the group must call this (a group's first lane
+// reads the lane before it, in another group or none, and does not write).
 template <int K>
 __device__ __forceinline__ void top_combine(const Reduced<K>& red, bool writer, const TopLevel<K>& to, int m) {
   constexpr int Q = Dim<K>::Q, KK = Dim<K>::KK;
@@ -810,21 +816,27 @@ __device__ __forceinline__ void zero_reduced(Reduced<K>& red) {
   red.fail = 0;
 }
 
-template <int K, int L>
+template <int K, int L, int SW>
 __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_top(LevelDev lv, Level0Args a, int level) {
   constexpr int PER = Dim<K>::Q + Dim<K>::KK + 2 * K;
+  constexpr int IPW = WAVE / SW;   // instances per wave
   extern __shared__ __align__(16) unsigned char smem[];
-  double* base = reinterpret_cast<double*>(smem) + (threadIdx.x / WAVE) * (TopCaps<L>::nodes * PER);
-  const int lane = lane_id();
-  for (int64_t tw = first_tile(a); tw < a.N; tw = next_tile(a, tw)) {
+  const int lane = lane_id() % SW;   // lane within the instance's group
+  const int sub = lane_id() / SW;    // the group within the wave
+  double* base = reinterpret_cast<double*>(smem) + ((threadIdx.x / WAVE) * IPW + sub) * (TopCaps<L, SW>::nodes * PER);
+  const int64_t groups = (a.N + IPW - 1) / IPW;
+  for (int64_t tw = first_tile(a); tw < groups; tw = next_tile(a, tw)) {
     // ragged batches: instances longest first (the plan's order), so the
     // longest chains start first; equal lengths: alternate the direction
-    const int64_t inst = a.order ? a.order[tw] : (a.rev ? a.N - 1 - tw : tw);
+    const int64_t slot = tw * IPW + sub;
+    const bool live = slot < a.N;
+    const int64_t si = live ? slot : a.N - 1;
+    const int64_t inst = a.order ? a.order[si] : (a.rev ? a.N - 1 - si : si);
     const int64_t off = lv.node_off[inst];
     const int64_t n = lv.node_off[inst + 1] - off;
     const int64_t c0 = lv.chunk_off[inst];
-    const int G = static_cast<int>(lv.chunk_off[inst + 1] - c0);   // <= 64 (checked on the host)
-    if (n == 0) continue;
+    const int G = static_cast<int>(lv.chunk_off[inst + 1] - c0);   // <= SW (checked on the host)
+    if (live && n > 0) {   // (no early continue: the groups of a wave share its loop)
     double xl[K], xr[K], xs[L][K];
     if (G > 1) {
       // 1. level lt: lane j reduces chunk j; separators into LDS level 1
@@ -842,7 +854,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_top(LevelDev lv, Level0
           reduce_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, red);
           if (red.fail) report_fail(a, inst, level, geo.a + red.fail - 1);
         }
-        top_combine<K>(red, lane > 0 && lane < G, top_level<K, L>(base, 1), lane - 1);
+        top_combine<K>(red, lane > 0 && lane < G, top_level<K, L, SW>(base, 1), lane - 1);
       }
       __builtin_amdgcn_s_waitcnt(0);
       __builtin_amdgcn_wave_barrier();
@@ -851,7 +863,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_top(LevelDev lv, Level0
       int64_t nl = G - 1;
       while (nl > L) {
         const int Gd = static_cast<int>((nl + L - 1) / L);
-        const TopLevel<K> cur = top_level<K, L>(base, d);
+        const TopLevel<K> cur = top_level<K, L, SW>(base, d);
         const ChunkGeom geo = chunk_geom(lane, nl, L);
         Reduced<K> red;
         zero_reduced<K>(red);
@@ -860,7 +872,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_top(LevelDev lv, Level0
           reduce_chunk<K, L>(S, geo.a, geo.b, geo.has_left, geo.has_right, red);
           if (red.fail) report_fail(a, inst, level + d, geo.a + red.fail - 1);
         }
-        top_combine<K>(red, lane > 0 && lane < Gd, top_level<K, L>(base, d + 1), lane - 1);
+        top_combine<K>(red, lane > 0 && lane < Gd, top_level<K, L, SW>(base, d + 1), lane - 1);
         __builtin_amdgcn_s_waitcnt(0);
         __builtin_amdgcn_wave_barrier();
         nl = Gd - 1;
@@ -868,7 +880,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_top(LevelDev lv, Level0
       }
       // 3. the top level: a single chunk, solved by lane 0
       {
-        const TopLevel<K> top = top_level<K, L>(base, d);
+        const TopLevel<K> top = top_level<K, L, SW>(base, d);
         if (lane == 0) {
 #pragma unroll
           for (int e = 0; e < K; ++e) { xl[e] = 0.0; xr[e] = 0.0; }
@@ -887,7 +899,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_top(LevelDev lv, Level0
       __builtin_amdgcn_wave_barrier();
       // 4. back-substitute the LDS levels below the top
       for (int dd = d - 1; dd >= 1; --dd) {
-        const TopLevel<K> cur = top_level<K, L>(base, dd), up = top_level<K, L>(base, dd + 1);
+        const TopLevel<K> cur = top_level<K, L, SW>(base, dd), up = top_level<K, L, SW>(base, dd + 1);
         const int64_t nd = top_nodes<L>(G, dd);
         const int Gd = static_cast<int>((nd + L - 1) / L);
         if (lane < Gd) {
@@ -919,7 +931,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_top(LevelDev lv, Level0
     // 5. level lt: back-substitute every chunk into HBM
     if (lane < G) {
       const ChunkGeom geo = chunk_geom(lane, n, L);
-      const TopLevel<K> up = top_level<K, L>(base, 1);
+      const TopLevel<K> up = top_level<K, L, SW>(base, 1);
 #pragma unroll
       for (int e = 0; e < K; ++e) {
         xl[e] = geo.has_left ? up.x[(lane - 1) * K + e] : 0.0;
@@ -945,6 +957,7 @@ __global__ void __launch_bounds__(256, SMNN_MIN_WAVES) k_top(LevelDev lv, Level0
 #pragma unroll
         for (int e = 0; e < K; ++e) x[(geo.b + 1) * K + e] = xr[e];
       }
+    }
     }
     // the next instance reuses the LDS slice
     __builtin_amdgcn_s_waitcnt(0);
@@ -1110,24 +1123,30 @@ hipError_t backsubN_t(int level, const LevelDev& l, const LevelDev* nx, const Le
   return hipGetLastError();
 }
 
+template <int K>
+constexpr int top_width() { return top_lanes(K); }
+
 template <int K, int L>
-size_t top_lds_bytes_t() {
-  return sizeof(double) * TopCaps<L>::nodes * (Dim<K>::Q + Dim<K>::KK + 2 * K);
+size_t top_lds_bytes_t() {   // per wave
+  constexpr int SW = top_width<K>();
+  return sizeof(double) * (WAVE / SW) * TopCaps<L, SW>::nodes * (Dim<K>::Q + Dim<K>::KK + 2 * K);
 }
 
 template <int K, int L>
 hipError_t top_t(int level, const LevelDev& l, const Level0Args& a, const Launch& cfg, hipStream_t st) {
+  constexpr int SW = top_width<K>();
   const size_t wb = top_lds_bytes_t<K, L>();
   int wpb = cfg.block / WAVE;
   while (wpb > 1 && wb * static_cast<size_t>(wpb) > static_cast<size_t>(cfg.lds_max)) --wpb;
   if (wb > static_cast<size_t>(cfg.lds_max)) return hipErrorInvalidConfiguration;
   Launch c = cfg;
   c.block = wpb * WAVE;
-  const dim3 grid(static_cast<unsigned>(grid_for(a.N, c))), block(c.block);   // one wave per instance
+  const int64_t groups = (a.N + WAVE / SW - 1) / (WAVE / SW);   // one wave per 64 / SW instances
+  const dim3 grid(static_cast<unsigned>(grid_for(groups, c))), block(c.block);
   Level0Args b = a;
   b.wpb = wpb;
   b.nwaves = static_cast<int64_t>(grid.x) * wpb;
-  hipLaunchKernelGGL((k_top<K, L>), grid, block, wb * wpb, st, l, b, level);
+  hipLaunchKernelGGL((k_top<K, L, SW>), grid, block, wb * wpb, st, l, b, level);
   return hipGetLastError();
 }
 #endif
