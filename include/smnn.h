@@ -67,7 +67,12 @@
  *                  end are written as 0); dw shares w's (per-row weights:
  *                  the gradient of every row's weight, the unused slots 0).
  * For a uniform one-variable batch these are contiguous (N, T, R+1),
- * (N, T), ... arrays.
+ * (N, T), ... arrays.  This natural layout is the only one: there is no
+ * lane-tiled layout (instances interleaved across lanes) and so no pack,
+ * unpack or layout-query calls.  The kernels give each wave a contiguous
+ * range of steps, which they copy into LDS with coalesced loads before any
+ * arithmetic, so the natural layout streams at the same rate a tiled one
+ * would and the caller's tensors are used as they are.
  *
  * Ownership.  The caller allocates and owns every buffer.  `factor`
  * (smnn_plan_sizes) is written by smnn_forward and read by smnn_backward of
@@ -76,7 +81,10 @@
  * workspaces.  The library allocates device memory only in
  * smnn_plan_create (plan metadata) and frees it in smnn_plan_destroy.
  * smnn_forward / smnn_backward allocate nothing, synchronise nothing and
- * read nothing back, so they can be captured into a hipGraph.
+ * read nothing back, so they can always be captured into a hipGraph (the
+ * counters some launches use are cleared by kernels, not memset nodes);
+ * there is therefore no "not capturable" status.  smnn_autotune, which
+ * times launches and synchronises, is a separate call made before capture.
  *
  * Errors.  Every call returns an smnn_status.  Argument errors are detected
  * on the host before anything is enqueued.  Numerical breakdown is reported
