@@ -276,6 +276,29 @@ def test_upper_levels_in_one_launch(mode):
         H.check(mode, m, kappa, bt.R)
 
 
+@pytest.mark.parametrize("mode", ["fp64r", "fp32r"])
+def test_upper_levels_four_instances_per_wave(mode):
+    # 4 x 4 blocks (R = 3) take 16 lanes per instance in the one-launch upper
+    # levels.  Chunks 4 / 4: T = 260 gives 16 level-1 chunks (the most a
+    # group takes); T = 261 (17 chunks) moves the launch up to level 2.  Seven
+    # and six instances leave the last wave's groups partly empty, and T = 5
+    # has no node at level 2.
+    for T, top in (([5, 17, 65, 100, 200, 257, 260], 1), ([5, 17, 65, 257, 260, 261], 2)):
+        bt = H.io_batch(gaussian_batch(len(T), T, R=3, seed=40 + len(T) + top, weights=(1.1, 0.9, 1.2), h0=0.05),
+                        mode)
+        gy = np.random.default_rng(top + 7).standard_normal(bt.c.shape)
+        if mode == "fp32r":
+            gy = gy.astype(np.float32).astype(np.float64)
+        ref = H.reference(bt, gy)
+        kappa = banded.cond(bt)
+        out = H.run(bt, mode, gy, chunk=4, chunk_upper=4)
+        assert out["plan"].top_level == top
+        m = H.compare(bt, out, ref, range(bt.n_inst))
+        _print("upper levels 4x4 %s top=%d" % (mode, top), H.summary(m))
+        assert (out["info"] == 0).all()
+        H.check(mode, m, kappa, bt.R)
+
+
 def test_failure_reported_per_instance_and_isolated():
     bt = gaussian_batch(4, [50, 300, 1000, 90], R=2, seed=3)
     clean = H.run(bt, "fp64r")
