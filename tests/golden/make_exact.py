@@ -32,6 +32,11 @@ GENERAL_CASES = [  # (R, V, Q, per-row weights, T list, seed)
     (1, 2, 2, False, [5, 9, 17], 913),
     (1, 2, 2, True, [5, 9, 17], 914),
     (1, 2, 1, False, [5, 9, 17], 915),
+    # wide blocks (chunks of 4 at every level): 6 x 6 with three variables and
+    # with two order-2 ones, 9 x 9 with per-row weights
+    (1, 3, 3, False, [5, 9, 17], 916),
+    (2, 2, 2, False, [5, 9, 17], 917),
+    (2, 3, 3, True, [5, 9, 13], 918),
 ]
 
 

@@ -66,7 +66,7 @@ def test_general_forms_ragged(R, V, Q, rows, chunk, upper, mode):
     assert (out["info"] == 0).all()
 
 
-@pytest.mark.parametrize("case", range(5))
+@pytest.mark.parametrize("case", range(8))
 def test_exact_general_fixture_elementwise(case):
     # per-row weights and coupled variables against the rational oracle's
     # values (tests/golden/exact_general.json): y and du0 (= w_init^2 lam, the
@@ -78,7 +78,8 @@ def test_exact_general_fixture_elementwise(case):
     # ones stay ~1e-17); raw errors are printed
     bt, gy, want = golden.load_exact_general(case)
     L = 4 if bt.block == 3 else 8 if bt.block == 2 else 4
-    out = H.run(bt, "fp64r", gy, chunk=L, chunk_upper=8 if bt.block != 3 else 4)
+    upper = 4 if bt.block == 3 or bt.block > 5 else 8   # wide blocks: chunks of 4 at every level
+    out = H.run(bt, "fp64r", gy, chunk=L, chunk_upper=upper)
     assert (out["info"] == 0).all()
     m = H.compare_general(bt, out, want, range(bt.n_inst))
     _print("exact general R=%d V=%d Q=%d rows=%s" % (bt.R, bt.V, bt.Q, bt.wrow is not None), H.summary(m))

@@ -193,10 +193,10 @@ def test_quad_oracle_reproduces_exact_fixture(case):
         assert _rel_max(q[key], want[key]) <= 2 ** -52, key
 
 
-@pytest.mark.parametrize("case", range(5))
+@pytest.mark.parametrize("case", range(8))
 def test_quad_oracle_reproduces_exact_general_fixture(case):
-    # tests/golden/exact_general.json: per-row weights and two coupled
-    # variables (App. A.1-A.2), rational oracle rounded to double
+    # tests/golden/exact_general.json: per-row weights and two or three
+    # coupled variables (App. A.1-A.2), rational oracle rounded to double
     from tests import fixtures
     bt, gy, want = fixtures.load_exact_general(case)
     q = banded.grad(bt, gy, quad=True)
