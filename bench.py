@@ -302,23 +302,34 @@ def copy_calibration():
 
 
 def copy_rate(reps=20):
-    """The calibration copy timed with events: the read + write rate that a
-    plain streaming kernel reaches on this GPU."""
+    """Plain streaming rates on this GPU, timed with events: the calibration
+    copy (1 read : 1 write) and elementwise kernels reading two and three
+    arrays per array written (2 : 1, 3 : 1), which bracket the gradient
+    kernel's mix (about 2.6 : 1).  These are the ceilings a kernel with that
+    read/write mix can reach, beside the published peak."""
     import torch
     n = 64 * 1024 * 1024
     x = torch.ones(n, dtype=torch.float64, device="cuda")
+    x2 = torch.ones_like(x)
+    x3 = torch.ones_like(x)
     y = torch.empty_like(x)
-    for _ in range(3):
-        y.copy_(x)
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(reps):
-        y.copy_(x)
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / reps
-    print(json.dumps({"copy_bytes_per_direction": n * 8, "copy_ms": round(ms, 4),
-                      "copy_gbs_read_plus_write": round(2 * n * 8 / (ms * 1e-3) / 1e9, 1)}), flush=True)
+    kinds = (("copy", 1, lambda: y.copy_(x)),
+             ("add", 2, lambda: torch.add(x, x2, out=y)),
+             ("addcmul", 3, lambda: torch.addcmul(x, x2, x3, out=y)))
+    out = {"bytes_per_array": n * 8}
+    for name, reads, fn in kinds:
+        for _ in range(3):
+            fn()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            fn()
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        out[name] = {"reads_per_write": reads, "ms": round(ms, 4),
+                     "gbs_read_plus_write": round((reads + 1) * n * 8 / (ms * 1e-3) / 1e9, 1)}
+    print(json.dumps(out), flush=True)
     return 0
 
 
