@@ -28,7 +28,8 @@ struct smnn_plan {
   std::vector<LevelDev> lev;     // device views; rec/rhs/x hold byte offsets until bound
   std::vector<size_t> rec_off, rhs_off, x_off;
   size_t factor_bytes = 0, workspace_bytes = 0;
-  size_t buf_off[2] = {0, 0}, dwp_off = 0, info_off = 0, queue_off = 0;
+  size_t buf_off[2] = {0, 0}, dwp_off = 0, dwq_off = 0, info_off = 0, queue_off = 0;
+  int dw_split = 1;               // workgroups per instance of the weight-gradient sum
   void* meta = nullptr;          // device metadata (chunk_inst, chunk_off, node_off of every level)
   const int32_t* order = nullptr;  // in meta: instances by decreasing T (ragged batches only)
   // launch tracing (smnn_trace_enable); mutable: recorded during const calls
@@ -60,6 +61,7 @@ struct Bound {
   std::vector<LevelDev> lev;
   void* buf[2];
   double* dwp;
+  double* dwq;
   uint32_t* info;
   uint32_t* queue;
 };
@@ -80,6 +82,7 @@ Bound bind(const smnn_plan* p, void* factor, void* workspace) {
   b.buf[0] = ws + p->buf_off[0];
   b.buf[1] = ws + p->buf_off[1];
   b.dwp = reinterpret_cast<double*>(ws + p->dwp_off);
+  b.dwq = reinterpret_cast<double*>(ws + p->dwq_off);
   b.info = reinterpret_cast<uint32_t*>(ws + p->info_off);
   b.queue = reinterpret_cast<uint32_t*>(ws + p->queue_off);
   return b;
@@ -357,6 +360,17 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   }
   p->dwp_off = wb;
   wb = align_up(wb + sizeof(double) * 3 * lv[0].chunks);
+  // The per-instance sums of those partials: batches of fewer than 512
+  // instances split each instance's chunks over several workgroups (each
+  // slice at least 1024 chunks), whose sums go through [N][split][3].
+  {
+    int64_t cmax = 0;
+    for (int64_t i = 0; i < p->N; ++i) cmax = std::max(cmax, lv[0].chunk_off[i + 1] - lv[0].chunk_off[i]);
+    const int64_t want = p->N >= 512 ? 1 : (512 + p->N - 1) / p->N;
+    p->dw_split = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, cmax / 1024)));
+  }
+  p->dwq_off = wb;
+  if (p->dw_split > 1) wb = align_up(wb + sizeof(double) * 3 * p->N * p->dw_split);
   p->info_off = wb;
   wb = align_up(wb + sizeof(uint32_t) * p->N);
   p->queue_off = wb;
@@ -583,7 +597,8 @@ smnn_status smnn_backward(const smnn_plan* p, const void* c, const void* b, cons
     }
   }
   const Tracer tr{p, st};
-  if (!p->rows) SMNN_LAUNCH(tr, a, SMNN_K_DW, 0, 0, 0, launch_dw_reduce(p->f32, bd.lev[0], a, st));
+  if (!p->rows)
+    SMNN_LAUNCH(tr, a, SMNN_K_DW, 0, 0, 0, launch_dw_reduce(p->f32, bd.lev[0], a, p->dw_split, bd.dwq, st));
   SMNN_HIP(launch_info_finalize(a, info, st));
   return SMNN_OK;
 }

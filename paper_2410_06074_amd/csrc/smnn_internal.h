@@ -126,7 +126,10 @@ constexpr int top_lanes(int K) { return K <= 3 ? 64 : 16; }
 hipError_t launch_top(int K, int L, int level, const LevelDev& l, const Level0Args& a, const Launch& cfg,
                       hipStream_t st);
 size_t top_lds_bytes(int K, int L);   // per wave
-hipError_t launch_dw_reduce(bool f32, const LevelDev& l0, const Level0Args& a, hipStream_t st);
+// Per-instance weight gradients from the per-chunk partials: `split`
+// workgroups per instance (partial sums in `part`, [N][split][3], when > 1).
+hipError_t launch_dw_reduce(bool f32, const LevelDev& l0, const Level0Args& a, int split, double* part,
+                            hipStream_t st);
 hipError_t launch_info_init(const Level0Args& a, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t st);
 

@@ -6,31 +6,58 @@
 namespace smnn {
 namespace {
 
-// Sum the per-chunk weight-gradient partials of each instance: one
-// workgroup per instance, strided per-thread sums then a fixed-shape tree in
-// LDS, so the result does not depend on scheduling.
+// Sum the per-chunk weight-gradient partials of each instance, in an order
+// that does not depend on scheduling: `split` workgroups per instance, each
+// summing one contiguous slice of the instance's chunks (strided per-thread
+// sums, then a fixed-shape tree in LDS).  With split == 1 the workgroup
+// writes the instance's result; otherwise its slice sum goes to `part` and
+// k_dw_final adds the slices of an instance in order.  (One workgroup per
+// instance left a batch of a few long instances on a few CUs, each summing
+// ~10^5 chunks.)
 template <class TIO>
-__global__ void __launch_bounds__(256) k_dw_reduce(LevelDev l0, Level0Args a) {
-  __shared__ double part[3][256];
-  const int64_t i = blockIdx.x;
+__global__ void __launch_bounds__(256) k_dw_reduce(LevelDev l0, Level0Args a, int split, double* part) {
+  __shared__ double sum[3][256];
+  const int64_t i = blockIdx.x / split;
+  const int p = static_cast<int>(blockIdx.x % split);
   const int tid = threadIdx.x;
+  const int64_t c0 = l0.chunk_off[i], c1 = l0.chunk_off[i + 1];
+  const int64_t span = (c1 - c0 + split - 1) / split;
+  const int64_t lo = c0 + p * span, hi = lo + span < c1 ? lo + span : c1;
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int64_t g = l0.chunk_off[i] + tid; g < l0.chunk_off[i + 1]; g += 256)
+  for (int64_t g = lo + tid; g < hi; g += 256)
 #pragma unroll
     for (int e = 0; e < 3; ++e) acc[e] += a.dw_part[g * 3 + e];
 #pragma unroll
-  for (int e = 0; e < 3; ++e) part[e][tid] = acc[e];
+  for (int e = 0; e < 3; ++e) sum[e][tid] = acc[e];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (tid < w)
 #pragma unroll
-      for (int e = 0; e < 3; ++e) part[e][tid] += part[e][tid + w];
+      for (int e = 0; e < 3; ++e) sum[e][tid] += sum[e][tid + w];
     __syncthreads();
   }
   if (tid == 0) {
-    TIO* dw = static_cast<TIO*>(a.dw);
+    if (split == 1) {
+      TIO* dw = static_cast<TIO*>(a.dw);
 #pragma unroll
-    for (int e = 0; e < 3; ++e) dw[i * 3 + e] = static_cast<TIO>(part[e][0]);
+      for (int e = 0; e < 3; ++e) dw[i * 3 + e] = static_cast<TIO>(sum[e][0]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 3; ++e) part[blockIdx.x * 3 + e] = sum[e][0];
+    }
+  }
+}
+
+template <class TIO>
+__global__ void k_dw_final(Level0Args a, int split, const double* part) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.N) return;
+  TIO* dw = static_cast<TIO*>(a.dw);
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    double t = 0.0;
+    for (int p = 0; p < split; ++p) t += part[(i * split + p) * 3 + e];
+    dw[i * 3 + e] = static_cast<TIO>(t);
   }
 }
 
@@ -52,10 +79,18 @@ __global__ void k_info_finalize(const uint32_t* ws, int32_t* info, int64_t N) {
 
 }  // namespace
 
-hipError_t launch_dw_reduce(bool f32, const LevelDev& l0, const Level0Args& a, hipStream_t st) {
-  const dim3 grid(static_cast<unsigned>(a.N)), block(256);
-  if (f32) hipLaunchKernelGGL(k_dw_reduce<float>, grid, block, 0, st, l0, a);
-  else hipLaunchKernelGGL(k_dw_reduce<double>, grid, block, 0, st, l0, a);
+hipError_t launch_dw_reduce(bool f32, const LevelDev& l0, const Level0Args& a, int split, double* part,
+                            hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>(a.N * split)), block(256);
+  if (f32) hipLaunchKernelGGL(k_dw_reduce<float>, grid, block, 0, st, l0, a, split, part);
+  else hipLaunchKernelGGL(k_dw_reduce<double>, grid, block, 0, st, l0, a, split, part);
+  if (split > 1) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 g2(static_cast<unsigned>((a.N + 63) / 64)), b2(64);
+    if (f32) hipLaunchKernelGGL(k_dw_final<float>, g2, b2, 0, st, a, split, part);
+    else hipLaunchKernelGGL(k_dw_final<double>, g2, b2, 0, st, a, split, part);
+  }
   return hipGetLastError();
 }
 

@@ -299,6 +299,25 @@ def test_upper_levels_four_instances_per_wave(mode):
         H.check(mode, m, kappa, bt.R)
 
 
+@pytest.mark.parametrize("mode", ["fp64r", "fp32r"])
+def test_weight_gradients_summed_over_several_workgroups(mode):
+    # few long instances: each instance's per-chunk weight-gradient partials
+    # are summed by several workgroups (slices of >= 1024 chunks) and the
+    # slices added in order; ragged lengths give unequal slices
+    T = [30000, 25000, 20001, 9000]
+    bt = H.io_batch(gaussian_batch(len(T), T, R=2, seed=77, weights=(1.1, 0.9, 1.2)), mode)
+    gy = np.random.default_rng(77).standard_normal(bt.c.shape)
+    if mode == "fp32r":
+        gy = gy.astype(np.float32).astype(np.float64)
+    ref = H.reference(bt, gy)
+    kappa = banded.cond(bt)
+    out = H.run(bt, mode, gy)
+    m = H.compare(bt, out, ref, range(bt.n_inst))
+    _print("dw split %s" % mode, H.summary(m))
+    assert (out["info"] == 0).all()
+    H.check(mode, m, kappa, bt.R)
+
+
 def test_failure_reported_per_instance_and_isolated():
     bt = gaussian_batch(4, [50, 300, 1000, 90], R=2, seed=3)
     clean = H.run(bt, "fp64r")
