@@ -57,6 +57,35 @@ int default_chunk(int K, bool upper, bool f32) {
   }
 }
 
+// Float I/O takes level-0 chunks of 8 from this many time steps on.  Below it
+// chunks of 8 leave too few tiles to fill the chip more than about twice and
+// the last round of waves idles most CUs: on 1536 x 1,000 steps chunk 4 was
+// faster (0.352 against 0.385 ms per fp32r step), while from 5e6 steps on
+// chunk 8 was 15-18 % faster.
+constexpr int64_t kFloatChunk8Steps = int64_t(1) << 22;
+
+// First level >= 1 from which one launch per solve can take the upper levels
+// (0: none): every instance has at most `lanes` chunks there, the level holds
+// at most 2^19 nodes, and it is not the last level (so that it replaces at
+// least two).  Level l has the chunk length L0 at l = 0 and L1 above.
+int top_start(const std::vector<int64_t>& T, int L0, int L1, int lanes) {
+  std::vector<int64_t> n = T;
+  for (int l = 0;; ++l) {
+    const int L = l == 0 ? L0 : L1;
+    int64_t gmax = 0, nodes = 0;
+    bool any_next = false;
+    for (auto& ni : n) {
+      const int64_t g = ni > 0 ? ceil_div(ni, L) : 0;
+      gmax = std::max(gmax, g);
+      nodes += ni;
+      ni = ni > L ? g - 1 : 0;
+      any_next = any_next || ni > 0;
+    }
+    if (l >= 1 && any_next && gmax <= lanes && nodes <= (int64_t(1) << 19)) return l;
+    if (!any_next) return 0;
+  }
+}
+
 struct Bound {
   std::vector<LevelDev> lev;
   void* buf[2];
@@ -249,17 +278,28 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   const bool wide = K > 5;
   if (form < 0) return SMNN_ERR_UNSUPPORTED;
   const bool f32 = d->mode == SMNN_MODE_FP32_REFINED;
-  const int L0 = d->chunk ? d->chunk : (wide ? 4 : default_chunk(K, false, f32));
-  const int L1 = d->chunk_upper ? d->chunk_upper : (wide ? 4 : default_chunk(K, true, f32));
   if (d->chunk < 0 || d->chunk_upper < 0) return SMNN_ERR_INVALID_ARG;
-  if (wide ? !(wide_supported(K, L0, form) && wide_supported(K, L1, form))
-           : !(supported0(K, L0, form) && supported(K, L1)))
-    return SMNN_ERR_UNSUPPORTED;
   std::vector<int64_t> T(static_cast<size_t>(d->n_inst));
+  int64_t steps = 0;
   for (int64_t i = 0; i < d->n_inst; ++i) {
     T[i] = d->steps ? d->steps[i] : d->steps_uniform;
     if (T[i] < 1 || T[i] > (int64_t(1) << 40)) return SMNN_ERR_INVALID_ARG;
+    steps += T[i];
   }
+  const int L0 = d->chunk ? d->chunk : (wide ? 4 : default_chunk(K, false, f32 && steps >= kFloatChunk8Steps));
+  int L1 = d->chunk_upper ? d->chunk_upper : (wide ? 4 : default_chunk(K, true, f32));
+  // 3 x 3 blocks: separator chunks of 4 where the one-launch upper levels
+  // start at the same level as with 8.  That launch's first and last sweeps
+  // then take 4 dependent steps per lane instead of 8 (1536 x 1,000 steps:
+  // 43 -> 31 us per solve, fp64r 0.456 -> 0.411 ms per step).  Where chunks
+  // of 4 would add a level below it (1536 x 10,000 steps), 8 stays faster.
+  if (!d->chunk_upper && !wide && K == 3 && L1 == 8) {
+    const int t8 = top_start(T, L0, 8, top_lanes(K)), t4 = top_start(T, L0, 4, top_lanes(K));
+    if (t4 > 0 && t8 > 0 && t4 <= t8) L1 = 4;
+  }
+  if (wide ? !(wide_supported(K, L0, form) && wide_supported(K, L1, form))
+           : !(supported0(K, L0, form) && supported(K, L1)))
+    return SMNN_ERR_UNSUPPORTED;
 
   smnn_plan* p = new (std::nothrow) smnn_plan;
   if (!p) return SMNN_ERR_HIP;
@@ -316,13 +356,8 @@ smnn_status smnn_plan_create(const smnn_plan_desc* d, smnn_plan** out) {
   // nodes.  Larger blocks hold a whole SIMD per wave, so they take four
   // instances per wave (at most 16 chunks each).
   const bool top_fits = K <= 3 ? K * L1 <= 24 : true;
-  if (!wide && top_fits && top_lds_bytes(K, L1) > 0 && top_lds_bytes(K, L1) <= static_cast<size_t>(lds_max)) {
-    for (size_t l = 1; l + 1 < lv.size() && p->top == 0; ++l) {
-      int64_t gmax = 0;
-      for (int64_t i = 0; i < d->n_inst; ++i) gmax = std::max(gmax, lv[l].chunk_off[i + 1] - lv[l].chunk_off[i]);
-      if (gmax <= top_lanes(K) && lv[l].nodes <= (int64_t(1) << 19)) p->top = static_cast<int>(l);
-    }
-  }
+  if (!wide && top_fits && top_lds_bytes(K, L1) > 0 && top_lds_bytes(K, L1) <= static_cast<size_t>(lds_max))
+    p->top = top_start(T, L0, L1, top_lanes(K));
   const int Q = K * (K + 1) / 2;
   // separator records: packed A and the coupling block; wide blocks keep
   // full K x K halves of A and the coupling block (3 K^2), and two halves of
