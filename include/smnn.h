@@ -136,8 +136,11 @@ typedef struct {
   int32_t mode;           /* smnn_mode */
   int32_t refine_steps;   /* refinement steps in the refined modes, 0..4; -1: default
                              (2 for SMNN_MODE_FP64_REFINED at order >= 3, else 1) */
-  int32_t chunk;          /* nodes per lane at level 0 (time steps; 4, 8 or 16); 0: default for the order and mode */
-  int32_t chunk_upper;    /* nodes per lane at the separator levels >= 1; 0: default for the order */
+  int32_t chunk;          /* nodes per lane at level 0 (time steps; 4, 8 or 16); 0: default for the order and
+                             mode (float I/O at 3 x 3 and 4 x 4 blocks: 8 from 2^22 steps per batch on, else 4) */
+  int32_t chunk_upper;    /* nodes per lane at the separator levels >= 1; 0: default for the order (3 x 3
+                             blocks: 4 where the single upper-level launch then starts at the same level
+                             as with 8, else 8); SMNN_Q_CHUNK / SMNN_Q_CHUNK_UPPER report the choice */
   int32_t block;          /* threads per workgroup (64..256, multiple of 64); 0: 64 */
   int32_t max_blocks;     /* >0: persistent launches of at most this many workgroups per
                              kernel, whose waves claim tiles from a device work queue
